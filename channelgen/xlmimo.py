@@ -1,0 +1,184 @@
+"""Non-stationary, spatially correlated XL-MIMO channels (paper Sec. II, eqs. 2-4).
+
+Model, per user k and instance (subcarrier):
+
+    h_k = sqrt(beta_k) * D_k * R^{1/2} g_k,     g_k ~ CN(0, I_M)
+
+  * R is block diagonal over the S subarrays of M/S antennas, with entries
+    r^|i-j| inside a subarray (exponential correlation). R^{1/2} g is realised
+    by the AR(1) recursion y_0 = g_0, y_i = r y_{i-1} + sqrt(1 - r^2) g_i, whose
+    matrix is the exact Cholesky factor of r^|i-j|.
+  * D_k is the binary visibility-region (VR) mask (eq. 4: Theta = D^1/2 R D^1/2);
+    the VR is a contiguous run of L_k subarrays, L_k uniform on the stated
+    range and its first subarray uniform over the valid positions.
+  * beta_k = d_k^-3.7 with d_k ~ U[10, 100] m ("literal" gain). The "normalised"
+    gain (d_k / 10 m)^-3.7 makes H^H H comparable to xi, so the solves are not
+    trivially well conditioned.
+
+The paper's per-antenna near-field path loss (eq. 3) and log-normal VR lengths
+are replaced by this per-user model, which is what the workloads specify.
+
+Every instance i of a workload draws from its own PCG64 stream seeded with
+SeedSequence([seed, i]), so any instance can be regenerated alone and
+bit-identically. Values are drawn in complex128 and rounded once to complex64;
+both the GPU path and the oracle consume the same complex64 values.
+
+Layout: a batch is returned as a complex64 array of shape [n, K, M]; row k of
+instance b is user k's channel over the M antennas, i.e. each instance is the
+column-major M x K matrix H (``instance_matrix`` gives the M x K view).
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass, field, replace
+
+import numpy as np
+
+
+@dataclass(frozen=True)
+class Workload:
+    name: str
+    M: int
+    S: int
+    K: int
+    r: float
+    vr: tuple            # (min, max) number of visible subarrays, inclusive
+    batch: int
+    snr_db: tuple = (10.0,)
+    xi: float | None = None   # fixed xi overrides the K/SNR rule
+    gain: str = "literal"     # "literal" or "normalised"
+    seed: int = 0
+    tol: float = 0.0
+    max_iter: int = 16
+    extra: dict = field(default_factory=dict)
+
+    def xi_values(self):
+        if self.xi is not None:
+            return [float(self.xi)]
+        return [xi_from_snr(self.K, s) for s in self.snr_db]
+
+
+def xi_from_snr(K, snr_db):
+    """Regularisation xi = K / SNR (SNR in dB), the workloads' rule."""
+    return float(K) / (10.0 ** (float(snr_db) / 10.0))
+
+
+WORKLOADS = {
+    # one plain instance: M=256 in 4 subarrays of 64, K=16, r=0.5, VR of 2-4
+    # subarrays, 10 dB, Jac-PCG to relative residual 1e-6 or 16 iterations
+    "single": Workload("single", M=256, S=4, K=16, r=0.5, vr=(2, 4), batch=1,
+                       snr_db=(10.0,), tol=1e-6, max_iter=16),
+    # 1024 subcarriers of M=1024 (8 x 128) and K=64, r=0.5, VR of 3-6,
+    # SNR 0/10/20 dB, 8 fixed iterations (plus a tolerance-1e-5 variant)
+    "batched": Workload("batched", M=1024, S=8, K=64, r=0.5, vr=(3, 6), batch=1024,
+                        snr_db=(0.0, 10.0, 20.0), tol=0.0, max_iter=8),
+    # 256 instances of M=4096 (16 x 256) and K=128, r=0.7, 10 dB; the VR
+    # length is not stated for this workload: 6-12 of 16 subarrays keeps the
+    # 3/8-6/8 visible fraction of the batched workload
+    "precision": Workload("precision", M=4096, S=16, K=128, r=0.7, vr=(6, 12),
+                          batch=256, snr_db=(10.0,), tol=1e-6, max_iter=64),
+    # 64 instances of M=8192 (32 x 256) and K=256, r=0.95, VR of 1-3,
+    # near-ZF regularisation xi = 1e-3
+    "stress": Workload("stress", M=8192, S=32, K=256, r=0.95, vr=(1, 3), batch=64,
+                       xi=1e-3, tol=1e-6, max_iter=1024),
+}
+
+
+def workload(name, **overrides):
+    w = WORKLOADS[name]
+    return replace(w, **overrides) if overrides else w
+
+
+def _rng(seed, index):
+    return np.random.Generator(np.random.PCG64(np.random.SeedSequence([int(seed), int(index)])))
+
+
+def _ar1_factor(Ms, r):
+    """Lower-triangular L with L L^T = [r^|i-j|] (the AR(1) recursion as a matrix)."""
+    i = np.arange(Ms)
+    expo = i[:, None] - i[None, :]
+    L = np.where(expo >= 0, np.power(float(r), np.maximum(expo, 0)), 0.0)
+    L[:, 1:] *= np.sqrt(1.0 - float(r) ** 2)
+    return L
+
+
+def channel_instance(M, S, K, r, vr, seed, index, gain="literal"):
+    """Draw one instance. Returns (H as complex64 [K, M], meta dict)."""
+    if M % S:
+        raise ValueError("M must be a multiple of S")
+    Ms = M // S
+    lo, hi = int(vr[0]), int(vr[1])
+    hi = min(hi, S)
+    lo = max(1, min(lo, hi))
+    rng = _rng(seed, index)
+    d = rng.uniform(10.0, 100.0, size=K)
+    vr_len = rng.integers(lo, hi + 1, size=K)
+    vr_start = np.array([rng.integers(0, S - L + 1) for L in vr_len])
+    g = (rng.standard_normal((K, S, Ms)) + 1j * rng.standard_normal((K, S, Ms))) / np.sqrt(2.0)
+    y = g @ _ar1_factor(Ms, r).T                      # correlate along antennas
+    mask = np.zeros((K, S), dtype=bool)
+    for k in range(K):
+        mask[k, vr_start[k]:vr_start[k] + vr_len[k]] = True
+    y = y * mask[:, :, None]
+    if gain == "literal":
+        beta = d ** -3.7
+    elif gain == "normalised":
+        beta = (d / 10.0) ** -3.7
+    else:
+        raise ValueError(gain)
+    h = (np.sqrt(beta)[:, None, None] * y).reshape(K, M)
+    meta = dict(distance=d, beta=beta, vr_start=vr_start, vr_len=vr_len, mask=mask)
+    return h.astype(np.complex64), meta
+
+
+def channel_batch(w: Workload, n=None, start=0, seed=None, gain=None):
+    """Instances start .. start+n-1 of workload w as complex64 [n, K, M]."""
+    n = w.batch if n is None else int(n)
+    seed = w.seed if seed is None else seed
+    gain = w.gain if gain is None else gain
+    out = np.empty((n, w.K, w.M), dtype=np.complex64)
+    for b in range(n):
+        out[b], _ = channel_instance(w.M, w.S, w.K, w.r, w.vr, seed, start + b, gain)
+    return out
+
+
+def instance_matrix(Hb):
+    """The M x K matrix H (complex128) of one instance stored as [K, M]."""
+    return np.asarray(Hb).T.astype(np.complex128)
+
+
+def serving_requests(rate_hz=2000.0, duration_s=11.0, seed=0, max_requests=None):
+    """Poisson request stream of the serving workload.
+
+    Each request: arrival time (exponential gaps at ``rate_hz``), M from
+    {256, 512, 1024, 2048, 4096}, K uniform on {8, 16, 32, 64, 128, 256} with
+    K <= M/8, 1-64 subcarriers, r ~ U[0.3, 0.9]; channels follow the
+    single-instance model (4 subarrays of M/4, VR of 2-4) at xi = K/10 (10 dB).
+    Channels are not drawn here -- ``request_channels`` draws them on demand.
+    """
+    rng = _rng(seed, 10 ** 9)
+    t = 0.0
+    reqs = []
+    while True:
+        t += rng.exponential(1.0 / rate_hz)
+        if t > duration_s:
+            break
+        M = int(rng.choice([256, 512, 1024, 2048, 4096]))
+        ks = [k for k in (8, 16, 32, 64, 128, 256) if k <= M // 8]
+        K = int(rng.choice(ks))
+        n_sub = int(rng.integers(1, 65))
+        r = float(rng.uniform(0.3, 0.9))
+        reqs.append(dict(t=t, M=M, K=K, n_sub=n_sub, r=r, S=4, vr=(2, 4),
+                         xi=xi_from_snr(K, 10.0), seed=int(seed) * 1000003 + len(reqs)))
+        if max_requests is not None and len(reqs) >= max_requests:
+            break
+    return reqs
+
+
+def request_channels(req):
+    """complex64 [n_sub, K, M] channels of one serving request."""
+    out = np.empty((req["n_sub"], req["K"], req["M"]), dtype=np.complex64)
+    for b in range(req["n_sub"]):
+        out[b], _ = channel_instance(req["M"], req["S"], req["K"], req["r"], req["vr"],
+                                     req["seed"], b)
+    return out
