@@ -1,0 +1,211 @@
+/*
+ * jacpcg.h -- C ABI of libjacpcg.so: the RZF precoder computed by
+ * Jacobi-preconditioned conjugate gradient, on one AMD Instinct MI355X (gfx950).
+ *
+ * The operations follow Xu et al., "Jac-PCG Based Low-Complexity Precoding for
+ * Extremely Large-Scale MIMO Systems":
+ *   - regularised Gram A = H^H H + xi I_K               (Sec. II, eq. 7: P_i)
+ *   - Jacobi-preconditioned CG on A X = B, C = diag(A)  (Sec. III-B, eq. 21,
+ *                                                        Algorithm 1)
+ *   - precoder W = beta_pow H X, beta_pow = sqrt(P_tx / ||H X||_F^2)
+ *                                                       (eq. 7, the power factor
+ *                                                        after it, and eq. 15)
+ *
+ * Conventions shared by every entry point
+ *   - Complex numbers are interleaved (re, im) pairs: jacpcg_c64 has the
+ *     storage of torch.complex64 / std::complex<float>, jacpcg_c128 that of
+ *     complex128.
+ *   - Matrix pointers are DEVICE pointers owned by the caller; the library never
+ *     frees them. Host pointers are marked "host".
+ *   - H (M x K per instance) is column-major: H[k * ldh + m] is antenna m of
+ *     user k (each user's channel vector h_k is contiguous), ldh >= M.
+ *   - A (K x K) is row-major with both triangles stored: A[i * lda + j] = A_ij,
+ *     lda >= K. A is Hermitian, so the row-major and column-major readings
+ *     differ only by conjugation.
+ *   - B, X (K x nrhs) and W (M x nrhs) are column-major: X[j * ldx + i].
+ *   - Batches are strided: instance b of a matrix starts at ptr + b * stride
+ *     (strides in elements of the pointee type).
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream). Work
+ *     is enqueued asynchronously on it; outputs are valid after the stream is
+ *     synchronised, unless the entry point says it synchronises.
+ *   - Every call returns a status code. Argument errors are detected on the
+ *     host before any device work and leave outputs untouched; the detail is
+ *     available from jacpcg_last_error() on the calling thread.
+ *   - Sizes: 1 <= K <= 256, 1 <= M, 1 <= nrhs <= 256, batch >= 0 (0 = no-op).
+ */
+#ifndef JACPCG_H
+#define JACPCG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct jacpcg_session jacpcg_session;
+typedef struct { float re, im; } jacpcg_c64;
+typedef struct { double re, im; } jacpcg_c128;
+
+/* Status codes. Positive: warnings, outputs are valid. Negative: errors. */
+enum {
+  JACPCG_OK = 0,
+  JACPCG_NOT_CONVERGED = 1,   /* some column missed `tol` within max_iter (Step 2 stop rule) */
+  JACPCG_NOT_READY = 2,       /* request still in flight */
+  JACPCG_E_INVALID_ARG = -1,
+  JACPCG_E_UNSUPPORTED = -2,
+  JACPCG_E_NO_DEVICE = -3,
+  JACPCG_E_OUT_OF_MEMORY = -4,
+  JACPCG_E_BREAKDOWN = -5,    /* p^H A p < 0 or non-finite: A not numerically HPD (eq. 18) */
+  JACPCG_E_HIP = -6,
+  JACPCG_E_BUDGET = -7,       /* request can never fit the session's HBM budget */
+  JACPCG_E_CANCELLED = -8,
+  JACPCG_E_TIMEOUT = -9
+};
+
+/* Gram precision (jacpcg_gram, rzf_precoder `precision`). */
+enum {
+  JACPCG_GRAM_FP32 = 0,       /* FP32 MFMA, FP32 accumulation */
+  JACPCG_GRAM_BF16X3 = 1,     /* split BF16 hi+lo, products hi*hi + hi*lo + lo*hi, FP32 accumulation */
+  JACPCG_GRAM_BF16X6 = 2,     /* split BF16 hi+mid+lo (exact split of FP32), six products, FP32 accumulation */
+  JACPCG_REFINE_FP64 = 0x100  /* rzf_precoder only: FP64-residual iterative refinement of X */
+};
+
+/* jacpcg_solve / rzf_precoder `flags`. */
+enum {
+  JACPCG_PRECOND_JACOBI = 0,  /* C = diag(A) (eq. 21) */
+  JACPCG_PRECOND_NONE = 1     /* C = I: plain CG, the method the paper compares against */
+};
+
+/* Kernel phases timed when profiling is on (jacpcg_session_set_profiling). */
+enum {
+  JACPCG_PHASE_GRAM = 0,
+  JACPCG_PHASE_SOLVE = 1,
+  JACPCG_PHASE_EPILOGUE = 2,
+  JACPCG_PHASE_GRAM64 = 3,
+  JACPCG_PHASE_RESIDUAL = 4,
+  JACPCG_NUM_PHASES = 5
+};
+
+/* ---- session ------------------------------------------------------------ */
+
+/* Create a session on HIP device `device`. hbm_budget_bytes caps the device
+ * memory the session may hold for workspaces and admitted requests (0 = no
+ * cap). tune_cache_path (host, nullable) names a JSON file of autotuned kernel
+ * choices, read at creation and rewritten when new shapes are tuned.
+ * Errors: E_INVALID_ARG (out == NULL, device < 0), E_NO_DEVICE (no such HIP
+ * device), E_HIP. On success *out owns device resources until destroy. */
+int jacpcg_session_create(int device, size_t hbm_budget_bytes, const char* tune_cache_path,
+                          jacpcg_session** out);
+
+/* Wait for all work of the session, stop its scheduler and free everything it
+ * allocated. NULL is ignored. */
+void jacpcg_session_destroy(jacpcg_session* s);
+
+/* Static description of a status code (never NULL). */
+const char* jacpcg_status_string(int status);
+
+/* Detail of the last failing call on this thread ("" if none). */
+const char* jacpcg_last_error(void);
+
+/* ABI version: major * 10000 + minor * 100 + patch. */
+int jacpcg_version(void);
+
+/* Turn per-phase kernel timing on (1) or off (0). When on, every kernel launch
+ * is bracketed by HIP events recorded on the launch stream. */
+int jacpcg_session_set_profiling(jacpcg_session* s, int enable);
+
+/* Host arrays of JACPCG_NUM_PHASES: accumulated milliseconds and launch counts
+ * of every timed kernel since the last reset (reset != 0 clears them).
+ * Synchronises the session's pending events. */
+int jacpcg_session_phase_times(jacpcg_session* s, double* ms_out, int64_t* launches_out, int reset);
+
+/* ---- the three steps ---------------------------------------------------- */
+
+/* Regularised Gram (eq. 7): A_b = H_b^H H_b + xi I_K for b < batch.
+ * H: column-major M x K (ldh >= M), A: row-major K x K (lda >= K), both
+ * triangles written, diagonal exactly real. diag (nullable, batch x K floats,
+ * contiguous per instance) receives Re diag(A) = ||h_k||^2 + xi, the Jacobi
+ * preconditioner of eq. 21. precision: JACPCG_GRAM_FP32 / _BF16X3 / _BF16X6.
+ * Errors: E_INVALID_ARG (NULL H/A, M < 1, K outside [1, 256], xi < 0 or not
+ * finite, ldh < M, lda < K, strides too small), E_UNSUPPORTED (precision). */
+int jacpcg_gram(jacpcg_session* s, void* stream, int batch, int M, int K,
+                const jacpcg_c64* H, int64_t ldh, int64_t stride_h,
+                float xi, int precision,
+                jacpcg_c64* A, int64_t lda, int64_t stride_a,
+                float* diag);
+
+/* Jacobi-preconditioned CG (Algorithm 1 with the step length of Step 3, C =
+ * diag(A) of eq. 21) on A_b X_b = B_b, every right-hand-side column solved
+ * independently from x = 0.
+ * A: row-major K x K Hermitian positive definite. B: column-major K x nrhs, or
+ * NULL for B = I_K (requires nrhs == K). X: column-major K x nrhs output.
+ * tol > 0: column j stops after the first iteration with
+ *   ||r_j||_2 <= tol * ||b_j||_2 (recurrence residual; Step 2's rule made
+ *   relative); tol == 0 runs exactly max_iter iterations (a column whose
+ *   residual underflows to exactly zero stops early). One iteration = one A p
+ *   product.
+ * flags: JACPCG_PRECOND_JACOBI (default) or JACPCG_PRECOND_NONE (plain CG).
+ * iters (nullable, batch x nrhs int32): iterations done per column.
+ * relres (nullable, batch x nrhs float): ||r_j|| / ||b_j|| at the stop.
+ * status (nullable, batch int32): per instance OK, NOT_CONVERGED (tol > 0 and a
+ *   column did not reach it) or E_BREAKDOWN (p^H A p < 0 or non-finite; that
+ *   column keeps its last x). p^H A p = 0 means p = 0 for HPD A, i.e. the
+ *   residual vanished: the column stops as converged. A zero column of B gives
+ *   x = 0 after 0 iterations.
+ * Errors: E_INVALID_ARG (NULL A/X, K or nrhs out of range, B NULL with
+ * nrhs != K, tol < 0, max_iter < 0, leading dimensions or strides too small). */
+int jacpcg_solve(jacpcg_session* s, void* stream, int batch, int K, int nrhs,
+                 const jacpcg_c64* A, int64_t lda, int64_t stride_a,
+                 const jacpcg_c64* B, int64_t ldb, int64_t stride_b,
+                 jacpcg_c64* X, int64_t ldx, int64_t stride_x,
+                 double tol, int max_iter, int flags,
+                 int32_t* iters, float* relres, int32_t* status);
+
+/* Per-call summary, filled on the host after the call synchronises. */
+typedef struct {
+  double max_rel_residual;   /* max over instances/columns of ||b - A x|| / ||b|| (recurrence, FP32) */
+  double max_refine_residual;/* refined path: max ||B - A64 X64||_F / ||B||_F at exit, else 0 */
+  int32_t max_iters;         /* max PCG iterations over all columns (first solve) */
+  int32_t refine_steps;      /* refined path: correction solves performed */
+  int32_t worst_status;      /* most severe per-instance status */
+  int32_t reserved;
+  double beta_pow_min, beta_pow_max;
+} jacpcg_stats;
+
+/* Whole path: A = H^H H + xi I (Gram in `precision`), X = A^{-1} B with B = I_K
+ * by Jacobi-PCG (tol, max_iter as in jacpcg_solve), then W = beta_pow H X with
+ * beta_pow = sqrt(power / ||H X||_F^2) per instance (eq. 7 and eq. 15).
+ * W: column-major M x K per instance (precoding vector g_k contiguous).
+ * precision | JACPCG_REFINE_FP64: after the FP32 solve, X is refined in FP64
+ *   (R = I - A64 X64 in FP64 with A64 the FP64 Gram, FP32 PCG on the
+ *   correction) until ||R||_F / ||I||_F <= refine_tol or 16 steps.
+ * X_out (nullable): column-major K x K c64 copy of X per instance (ld K,
+ *   stride K*K). X64_out (nullable): the same in c128 (refined path; the FP32
+ *   solution widened otherwise). flags: as jacpcg_solve.
+ * stats (host, nullable): when given, the call synchronises `stream` and fills
+ *   it. The refined path always synchronises (host-driven convergence test).
+ * Returns the worst per-instance status when it synchronises, else OK.
+ * Errors: as jacpcg_gram and jacpcg_solve; power <= 0; refine_tol < 0. */
+int rzf_precoder(jacpcg_session* s, void* stream, int batch, int M, int K,
+                 const jacpcg_c64* H, int64_t ldh, int64_t stride_h,
+                 double xi, double power, double tol, int max_iter, int precision, int flags,
+                 double refine_tol,
+                 jacpcg_c64* W, int64_t ldw, int64_t stride_w,
+                 jacpcg_c64* X_out, jacpcg_c128* X64_out, jacpcg_stats* stats);
+
+/* The same result computed the plain way, one instance at a time: per instance
+ * one Gram launch, one launch per PCG iteration (with a host-side convergence
+ * check after each when tol > 0), then the precoder launch. The baseline the
+ * batched path is measured against. FP32 Gram only, no refinement. */
+int rzf_precoder_plain(jacpcg_session* s, void* stream, int batch, int M, int K,
+                       const jacpcg_c64* H, int64_t ldh, int64_t stride_h,
+                       double xi, double power, double tol, int max_iter, int flags,
+                       jacpcg_c64* W, int64_t ldw, int64_t stride_w,
+                       jacpcg_c64* X_out, jacpcg_stats* stats);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* JACPCG_H */

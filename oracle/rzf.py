@@ -139,8 +139,9 @@ def jacpcg(A, B=None, tol=0.0, max_iter=16, precond="jacobi"):
         as ||r_j|| <= tol * ||b_j|| after an update. tol = 0 runs exactly
         ``max_iter`` iterations unless the residual becomes exactly zero;
       * one iteration is one product A m (Algorithm 1's counter t);
-      * a step with m^H A m <= 0 or not finite is a breakdown: the column stops
-        with its last x and status BREAKDOWN.
+      * a step with m^H A m < 0 or not finite is a breakdown: the column stops
+        with its last x and status BREAKDOWN. m^H A m = 0 means m = 0 for HPD A
+        (eq. 18), i.e. the residual vanished: the column stops as converged.
 
     Returns a dict with X (K x n), iters (n,), relres (n,) from the recurrence
     residual, true_relres (n,) = ||b - A x|| / ||b||, status (n,) per column,
@@ -178,8 +179,13 @@ def jacpcg(A, B=None, tol=0.0, max_iter=16, precond="jacobi"):
         for t in range(1, max_iter + 1):
             q = A @ p
             gamma = float(np.vdot(p, q).real)
-            if not (gamma > 0.0) or not np.isfinite(gamma):
+            if not np.isfinite(gamma) or gamma < 0.0:
                 status[j] = BREAKDOWN
+                break
+            if gamma == 0.0:
+                # For HPD A, p^H A p = 0 only for p = 0 (eq. 18), i.e. the
+                # residual has vanished: the column has converged.
+                converged = True
                 break
             alpha = rho / gamma
             x = x + alpha * p
@@ -190,6 +196,10 @@ def jacpcg(A, B=None, tol=0.0, max_iter=16, precond="jacobi"):
                 break
             z = r / d
             rho_next = float(np.vdot(r, z).real)
+            if rho_next == 0.0:
+                # r^H D^{-1} r = 0 with D > 0 only for r = 0: converged.
+                converged = True
+                break
             p = z + (rho_next / rho) * p
             rho = rho_next
         X[:, j] = x

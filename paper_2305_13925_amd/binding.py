@@ -1,0 +1,292 @@
+"""ctypes binding of libjacpcg.so with the names of its C ABI.
+
+Argument marshalling only: torch tensors supply device memory and the stream;
+every step of the precoder runs in the library's HIP kernels. Layout rules
+(see include/jacpcg.h):
+
+  H  complex64 [batch, K, M]   (each instance column-major M x K)
+  A  complex64 [batch, K, K]   (row-major, both triangles)
+  B, X complex64 [batch, n, K] (column-major K x n)
+  W  complex64 [batch, n, M]   (column-major M x n)
+
+There is no fallback: when the library is missing or no GPU is present the
+calls raise.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libjacpcg.so")
+
+# status codes
+OK = 0
+NOT_CONVERGED = 1
+NOT_READY = 2
+E_INVALID_ARG = -1
+E_UNSUPPORTED = -2
+E_NO_DEVICE = -3
+E_OUT_OF_MEMORY = -4
+E_BREAKDOWN = -5
+E_HIP = -6
+E_BUDGET = -7
+E_CANCELLED = -8
+E_TIMEOUT = -9
+
+GRAM_FP32 = 0
+GRAM_BF16X3 = 1
+GRAM_BF16X6 = 2
+REFINE_FP64 = 0x100
+PRECOND_JACOBI = 0
+PRECOND_NONE = 1
+
+PHASES = ("gram", "solve", "epilogue", "gram64", "residual")
+
+_i64 = C.c_int64
+_vp = C.c_void_p
+
+
+class JacpcgStats(C.Structure):
+    _fields_ = [
+        ("max_rel_residual", C.c_double),
+        ("max_refine_residual", C.c_double),
+        ("max_iters", C.c_int32),
+        ("refine_steps", C.c_int32),
+        ("worst_status", C.c_int32),
+        ("reserved", C.c_int32),
+        ("beta_pow_min", C.c_double),
+        ("beta_pow_max", C.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+class JacpcgError(RuntimeError):
+    def __init__(self, code, message):
+        super().__init__(f"{status_string(code)} ({code}): {message}")
+        self.code = code
+
+
+_lib = None
+
+
+def _declare(lib):
+    lib.jacpcg_version.restype = C.c_int
+    lib.jacpcg_last_error.restype = C.c_char_p
+    lib.jacpcg_status_string.restype = C.c_char_p
+    lib.jacpcg_status_string.argtypes = [C.c_int]
+    lib.jacpcg_session_create.argtypes = [C.c_int, C.c_size_t, C.c_char_p, C.POINTER(_vp)]
+    lib.jacpcg_session_destroy.argtypes = [_vp]
+    lib.jacpcg_session_destroy.restype = None
+    lib.jacpcg_session_set_profiling.argtypes = [_vp, C.c_int]
+    lib.jacpcg_session_phase_times.argtypes = [_vp, C.POINTER(C.c_double), C.POINTER(_i64), C.c_int]
+    lib.jacpcg_gram.argtypes = [_vp, _vp, C.c_int, C.c_int, C.c_int, _vp, _i64, _i64, C.c_float, C.c_int,
+                                _vp, _i64, _i64, _vp]
+    lib.jacpcg_solve.argtypes = [_vp, _vp, C.c_int, C.c_int, C.c_int, _vp, _i64, _i64, _vp, _i64, _i64,
+                                 _vp, _i64, _i64, C.c_double, C.c_int, C.c_int, _vp, _vp, _vp]
+    lib.rzf_precoder.argtypes = [_vp, _vp, C.c_int, C.c_int, C.c_int, _vp, _i64, _i64, C.c_double, C.c_double,
+                                 C.c_double, C.c_int, C.c_int, C.c_int, C.c_double, _vp, _i64, _i64, _vp, _vp,
+                                 C.POINTER(JacpcgStats)]
+    lib.rzf_precoder_plain.argtypes = [_vp, _vp, C.c_int, C.c_int, C.c_int, _vp, _i64, _i64, C.c_double,
+                                       C.c_double, C.c_double, C.c_int, C.c_int, _vp, _i64, _i64, _vp,
+                                       C.POINTER(JacpcgStats)]
+    for name in ("jacpcg_session_create", "jacpcg_session_set_profiling", "jacpcg_session_phase_times",
+                 "jacpcg_gram", "jacpcg_solve", "rzf_precoder", "rzf_precoder_plain"):
+        getattr(lib, name).restype = C.c_int
+    return lib
+
+
+def lib():
+    """The loaded library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2305_13925_amd.build`")
+        _lib = _declare(C.CDLL(LIB_PATH))
+    return _lib
+
+
+def status_string(code):
+    return lib().jacpcg_status_string(int(code)).decode()
+
+
+def last_error():
+    return lib().jacpcg_last_error().decode()
+
+
+def _check(rc):
+    if rc < 0:
+        raise JacpcgError(rc, last_error())
+    return rc
+
+
+# ---------------------------------------------------------------------------
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _require(t, name, dtype, shape=None):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device (HIP) tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+
+
+class Session:
+    """jacpcg_session_create / jacpcg_session_destroy."""
+
+    def __init__(self, device=0, hbm_budget_bytes=0, tune_cache_path=None):
+        h = _vp()
+        path = tune_cache_path.encode() if tune_cache_path else None
+        _check(lib().jacpcg_session_create(int(device), int(hbm_budget_bytes), path, C.byref(h)))
+        self.handle = h
+        self.device = device
+
+    def close(self):
+        if self.handle:
+            lib().jacpcg_session_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def set_profiling(self, enable=True):
+        _check(lib().jacpcg_session_set_profiling(self.handle, int(bool(enable))))
+
+    def phase_times(self, reset=False):
+        ms = (C.c_double * 5)()
+        cnt = (_i64 * 5)()
+        _check(lib().jacpcg_session_phase_times(self.handle, ms, cnt, int(bool(reset))))
+        return {PHASES[i]: (ms[i], cnt[i]) for i in range(5)}
+
+
+def jacpcg_gram(session, H, xi, precision=GRAM_FP32, A=None, diag=None, stream=None):
+    """A = H^H H + xi I for H complex64 [batch, K, M]; returns A [batch, K, K]."""
+    torch = _torch()
+    _require(H, "H", torch.complex64)
+    batch, K, M = H.shape
+    if A is None:
+        A = torch.empty((batch, K, K), dtype=torch.complex64, device=H.device)
+    _require(A, "A", torch.complex64, (batch, K, K))
+    if diag is not None:
+        _require(diag, "diag", torch.float32, (batch, K))
+    _check(lib().jacpcg_gram(session.handle, _stream(stream), batch, M, K, _ptr(H), M, K * M, float(xi),
+                             int(precision), _ptr(A), K, K * K, _ptr(diag)))
+    return A
+
+
+def jacpcg_solve(session, A, B=None, tol=0.0, max_iter=16, flags=PRECOND_JACOBI, X=None, iters=None,
+                 relres=None, status=None, stream=None):
+    """X = A^{-1} B by Jacobi-PCG. A [batch, K, K]; B [batch, n, K] or None (identity).
+
+    Returns X [batch, n, K]; iters/relres [batch, n] and status [batch] are
+    filled when given."""
+    torch = _torch()
+    _require(A, "A", torch.complex64)
+    batch, K, _ = A.shape
+    n = K if B is None else B.shape[1]
+    if B is not None:
+        _require(B, "B", torch.complex64, (batch, n, K))
+    if X is None:
+        X = torch.empty((batch, n, K), dtype=torch.complex64, device=A.device)
+    _require(X, "X", torch.complex64, (batch, n, K))
+    if iters is not None:
+        _require(iters, "iters", torch.int32, (batch, n))
+    if relres is not None:
+        _require(relres, "relres", torch.float32, (batch, n))
+    if status is not None:
+        _require(status, "status", torch.int32, (batch,))
+    _check(lib().jacpcg_solve(session.handle, _stream(stream), batch, K, n, _ptr(A), K, K * K, _ptr(B), K,
+                              n * K, _ptr(X), K, n * K, float(tol), int(max_iter), int(flags), _ptr(iters),
+                              _ptr(relres), _ptr(status)))
+    return X
+
+
+def rzf_precoder(session, H, xi, power=1.0, tol=0.0, max_iter=16, precision=GRAM_FP32, flags=PRECOND_JACOBI,
+                 refine_tol=1e-10, W=None, X_out=None, X64_out=None, stats=False, stream=None):
+    """W = beta_pow H A^{-1} (Jacobi-PCG), H complex64 [batch, K, M] -> W [batch, K, M].
+
+    Returns W, or (W, stats dict, return code) when stats=True (synchronises)."""
+    torch = _torch()
+    _require(H, "H", torch.complex64)
+    batch, K, M = H.shape
+    if W is None:
+        W = torch.empty((batch, K, M), dtype=torch.complex64, device=H.device)
+    _require(W, "W", torch.complex64, (batch, K, M))
+    if X_out is not None:
+        _require(X_out, "X_out", torch.complex64, (batch, K, K))
+    if X64_out is not None:
+        _require(X64_out, "X64_out", torch.complex128, (batch, K, K))
+    st = JacpcgStats() if stats else None
+    rc = _check(lib().rzf_precoder(session.handle, _stream(stream), batch, M, K, _ptr(H), M, K * M, float(xi),
+                                   float(power), float(tol), int(max_iter), int(precision), int(flags),
+                                   float(refine_tol), _ptr(W), M, K * M, _ptr(X_out), _ptr(X64_out),
+                                   C.byref(st) if st is not None else None))
+    if stats:
+        return W, st.as_dict(), rc
+    return W
+
+
+def rzf_precoder_plain(session, H, xi, power=1.0, tol=0.0, max_iter=16, flags=PRECOND_JACOBI, W=None, X_out=None,
+                       stats=False, stream=None):
+    """The same precoder, one instance at a time with one launch per iteration."""
+    torch = _torch()
+    _require(H, "H", torch.complex64)
+    batch, K, M = H.shape
+    if W is None:
+        W = torch.empty((batch, K, M), dtype=torch.complex64, device=H.device)
+    _require(W, "W", torch.complex64, (batch, K, M))
+    if X_out is not None:
+        _require(X_out, "X_out", torch.complex64, (batch, K, K))
+    st = JacpcgStats() if stats else None
+    rc = _check(lib().rzf_precoder_plain(session.handle, _stream(stream), batch, M, K, _ptr(H), M, K * M,
+                                         float(xi), float(power), float(tol), int(max_iter), int(flags), _ptr(W),
+                                         M, K * M, _ptr(X_out), C.byref(st) if st is not None else None))
+    if stats:
+        return W, st.as_dict(), rc
+    return W
+
+
+def exported_symbols():
+    """Names declared in include/jacpcg.h (parsed from the header)."""
+    import re
+    hdr = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "jacpcg.h")
+    text = open(hdr).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\**\s*(\w+)\s*\(", text, flags=re.M)))
+
+
+def to_numpy_instance(t):
+    """Host copy of one [n, rows] column-major instance as a rows x n complex128 matrix."""
+    return np.asarray(t.detach().cpu().numpy()).T.astype(np.complex128)

@@ -1,0 +1,123 @@
+// Shared declarations of the gfx950 kernels and the host runtime of libjacpcg.
+//
+// Matrix-core conventions used by every kernel (gfx950, wave64):
+//   v_mfma_f32_32x32x2_f32   A-operand: lane l holds A[l%32][l/32]
+//                            B-operand: lane l holds B[l/32][l%32]
+//                            result reg r of lane l is D[8*(r/4) + 4*(l/32) + r%4][l%32]
+//   v_mfma_f32_32x32x16_bf16 A-operand: lane l holds A[l%32][8*(l/32) + e], e < 8
+//                            B-operand: lane l holds B[8*(l/32) + e][l%32]; result as above
+//   v_mfma_f64_16x16x4_f64   A-operand: lane l holds A[l%16][l/16]
+//                            B-operand: lane l holds B[l/16][l%16]
+//                            result reg r of lane l is D[l/16 + 4*r][l%16]
+// Complex products are formed from real MFMAs; the k dimension of one MFMA
+// carries either the (re, im) parts of one complex term or two different
+// complex terms, as documented in each kernel.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace jacpcg {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int kMaxK = 256;
+constexpr int kMaxNrhs = 256;
+
+// Row (within a 32x32 tile) of result register r in lane l of a 32x32 MFMA.
+__host__ __device__ constexpr int d32_row(int r, int half) { return 8 * (r >> 2) + 4 * half + (r & 3); }
+
+// Severity order of per-instance statuses: BREAKDOWN > NOT_CONVERGED > OK.
+constexpr int kStatusOk = 0;
+constexpr int kStatusNotConverged = 1;
+constexpr int kStatusBreakdown = -5;
+
+// ---------------------------------------------------------------------------
+// Launch descriptors (host -> kernels). Pointers are device pointers.
+// ---------------------------------------------------------------------------
+struct GramLaunch {
+  const float2* H; int64_t ldh, stride_h;
+  int batch, M, K;
+  float xi;
+  float2* A; int64_t lda, stride_a;
+  float* diag;      // batch x K, Re diag(A) (nullable)
+  float* gdiag;     // batch x K, diag(H^H H) without xi (nullable)
+  int precision;    // 0 fp32, 1 bf16x3, 2 bf16x6
+  int m_split;      // waves per workgroup that split the antenna range (tuned)
+};
+
+// Per-workgroup resumable PCG state for chunked launches.
+struct PcgState {
+  float* vec;       // per WG: 6 arrays (x, r, p; re/im) of KT*16*64 floats
+  float* col;       // per WG: 8 x 32 floats of per-column scalars
+  int32_t* done;    // per WG: 1 when the WG has finished all its columns
+};
+
+struct PcgLaunch {
+  const float2* A; int64_t lda, stride_a;
+  const float2* B; int64_t ldb, stride_b;   // NULL => identity
+  float2* X; int64_t ldx, stride_x;
+  int batch, K, nrhs;
+  float tol;                                // 0 => fixed max_iter
+  int max_iter;
+  int precond_none;
+  int32_t* iters; float* relres;            // batch x nrhs (nullable)
+  int32_t* wg_status;                       // per workgroup worst status (nullable)
+  const float* gdiag;                       // nullable: enables the ||H X||^2 pass
+  float* fpart;                             // per workgroup sum_j x_j^H G x_j
+  PcgState st;                              // chunked mode when st.vec != NULL
+  int chunk;                                // iterations in this launch (chunked mode)
+  int first;                                // chunked mode: 1 on the first launch
+};
+
+struct PrecoderLaunch {
+  const float2* H; int64_t ldh, stride_h;
+  const float2* X; int64_t ldx, stride_x;
+  float2* W; int64_t ldw, stride_w;
+  int batch, M, K, nrhs;
+  const float* fpart; int ncb;              // per instance: ncb partial ||H X||^2 terms
+  float power;
+  float* beta_out;                          // batch (nullable)
+};
+
+struct Gram64Launch {
+  const float2* H; int64_t ldh, stride_h;
+  int batch, M, K;
+  double xi;
+  double2* A64;                             // batch x K x K row-major, ld K
+};
+
+struct ResidualLaunch {
+  const double2* A64;                       // batch x K x K, ld K
+  const double2* X64;                       // batch x K x n col-major, ld K
+  int batch, K, nrhs;
+  float2* R32;                              // scaled residual, col-major ld K (next RHS)
+  float* scale;                             // batch x n: ||r_j|| used to scale R32
+  double* rnorm2;                           // batch: ||R||_F^2
+};
+
+struct AccumulateLaunch {
+  double2* X64; const float2* E; const float* scale;
+  int batch, K, nrhs;
+  int first;                                // X64 = E * scale instead of +=
+  float2* X32;                              // nullable: rounded copy
+};
+
+// Kernel launchers (defined in the .hip files). All return hipError_t of the
+// launch itself.
+hipError_t launch_gram(const GramLaunch& g, hipStream_t s);
+hipError_t launch_pcg(const PcgLaunch& p, hipStream_t s, int* wg_count_out);
+int pcg_workgroups(int batch, int K, int nrhs);
+size_t pcg_state_floats_per_wg(int K);
+hipError_t launch_status_reduce(const int32_t* wg_status, int ncb, int batch, int32_t* status, hipStream_t s);
+hipError_t launch_precoder(const PrecoderLaunch& e, hipStream_t s);
+hipError_t launch_gram64(const Gram64Launch& g, hipStream_t s);
+hipError_t launch_residual(const ResidualLaunch& r, hipStream_t s);
+hipError_t launch_accumulate(const AccumulateLaunch& a, hipStream_t s);
+hipError_t launch_widen(const float2* X, int64_t ldx, int64_t stride_x, int batch, int K, int n,
+                        double2* out, hipStream_t s);
+
+}  // namespace jacpcg

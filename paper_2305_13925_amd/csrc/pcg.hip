@@ -1,0 +1,405 @@
+// Jacobi-preconditioned conjugate gradient (Sec. III-B, eq. 21, Algorithm 1 with
+// the standard PCG step length of Step 3) for a batch of K x K Hermitian
+// positive definite systems A X = B with many right-hand sides, as one
+// persistent launch: every iteration runs inside the kernel.
+//
+// Decomposition: the columns of B are independent PCG solves that share A, so a
+// workgroup owns (instance b, block of 32 right-hand sides) and all of its
+// iterations. KT = ceil(K/32) waves; wave w owns rows [32w, 32w+32) of the
+// solution, residual and direction for the block's 32 columns, held in
+// registers in the 32x32 MFMA result layout. The direction block P (K x 32)
+// lives in LDS and is the B-operand of the per-iteration product Q = A P.
+//
+// Q = A P on v_mfma_f32_32x32x2_f32: the two k slots of one MFMA carry the
+// complex terms k = s (slot 0) and k = s + K/2 (slot 1), so each lane walks one
+// contiguous half-row of A. Per step four real MFMAs form
+//   Re Q += Re A Re P - Im A Im P,   Im Q += Re A Im P + Im A Re P.
+// For K <= 64 each wave keeps its 32 rows of A in registers for the whole
+// solve; larger K streams the rows from L2 every iteration.
+//
+// Per iteration and column j (reductions are shuffles + LDS, fixed order):
+//   gamma_j = Re p_j^H q_j;  alpha_j = rho_j / gamma_j
+//   x_j += alpha_j p_j;  r_j -= alpha_j q_j
+//   stop when ||r_j|| <= tol ||b_j||  (tol = 0: fixed iteration count)
+//   z_j = D^{-1} r_j;  rho'_j = Re r_j^H z_j;  p_j = z_j + (rho'_j / rho_j) p_j
+// gamma_j < 0 or non-finite flags a breakdown and freezes the column;
+// gamma_j = 0 (p_j = 0 for HPD A: the residual underflowed) ends it as converged.
+//
+// Optional final pass for the precoder's power normalisation: with G = H^H H
+// (A with its diagonal replaced by diag(H^H H), passed in `gdiag`), every
+// workgroup writes sum over its columns of x_j^H G x_j = ||H X||_F^2 part,
+// computed without subtracting xi from A (no cancellation when xi >> ||h||^2).
+#include "device_util.hpp"
+
+namespace jacpcg {
+namespace {
+
+// Sum of one float per column over the two lane halves and all waves; every
+// lane receives the total of its column. One barrier.
+template <int KT, int NS>
+__device__ __forceinline__ void col_reduce(float (&v)[NS], float (*red)[KT][32], int w, int jl, int half) {
+#pragma unroll
+  for (int q = 0; q < NS; ++q) v[q] += __shfl_xor(v[q], 32);
+  if (half == 0) {
+#pragma unroll
+    for (int q = 0; q < NS; ++q) red[q][w][jl] = v[q];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NS; ++q) {
+    float t = 0.f;
+#pragma unroll
+    for (int ww = 0; ww < KT; ++ww) t += red[q][ww][jl];
+    v[q] = t;
+  }
+}
+
+// Q = A' P, A' the wave's 32 rows of A (with the diagonal entry zeroed when
+// `zero_diag`), P from LDS.
+template <int KT, bool AREG>
+__device__ __forceinline__ void apply_a(floatx16& qr, floatx16& qi, const float* ar, const float* ai,
+                                        const float2* __restrict__ arow, int klim, bool zero_diag, int diag_s,
+                                        const float2 (*Psh)[32], int half, int jl) {
+  constexpr int KH = KT * 16;
+  qr = zero16();
+  qi = zero16();
+  if constexpr (AREG) {
+#pragma unroll
+    for (int s = 0; s < KH; ++s) {
+      const float2 pv = Psh[half * KH + s][jl];
+      const float a_r = (zero_diag && s == diag_s) ? 0.f : ar[s];
+      const float a_i = (zero_diag && s == diag_s) ? 0.f : ai[s];
+      qr = mfma32(a_r, pv.x, qr);
+      qr = mfma32(a_i, -pv.y, qr);
+      qi = mfma32(a_r, pv.y, qi);
+      qi = mfma32(a_i, pv.x, qi);
+    }
+  } else {
+    for (int s0 = 0; s0 < KH; s0 += 8) {
+      float2 av[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int s = s0 + e;
+        av[e] = (s < klim && !(zero_diag && s == diag_s)) ? arow[s] : make_float2(0.f, 0.f);
+      }
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const float2 pv = Psh[half * KH + s0 + e][jl];
+        qr = mfma32(av[e].x, pv.x, qr);
+        qr = mfma32(av[e].y, -pv.y, qr);
+        qi = mfma32(av[e].x, pv.y, qi);
+        qi = mfma32(av[e].y, pv.x, qi);
+      }
+    }
+  }
+}
+
+template <int KT, bool AREG>
+__global__ __launch_bounds__(KT * 64) void pcg_f32_kernel(PcgLaunch p) {
+  constexpr int KP = KT * 32;
+  constexpr int KH = KT * 16;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int jl = lane & 31, half = lane >> 5;
+  const int ncb = (p.nrhs + 31) >> 5;
+  const int L = xcd_remap(blockIdx.x, gridDim.x);
+  const int b = L / ncb, cb = L - b * ncb;
+  const int K = p.K;
+  const int j = cb * 32 + jl;
+  const bool jvalid = j < p.nrhs;
+
+  __shared__ float2 Psh[KP][32];
+  __shared__ float red[3][KT][32];
+
+  const bool chunked = p.st.vec != nullptr;
+  // A workgroup that already finished in an earlier chunk has nothing to do.
+  if (chunked && !p.first && p.st.done[L]) return;
+
+  const float2* Ab = p.A + (int64_t)b * p.stride_a;
+  // A-operand row of this lane and its contiguous half-row.
+  const int ia = w * 32 + jl;
+  const int klim = (ia < K) ? max(0, min(KH, K - half * KH)) : 0;
+  const float2* arow = Ab + (int64_t)(ia < K ? ia : 0) * p.lda + half * KH;
+  const int diag_s = ia - half * KH;  // step holding A[ia][ia] in this lane, if in [0, KH)
+
+  float ar[AREG ? KH : 1], ai[AREG ? KH : 1];
+  if constexpr (AREG) {
+#pragma unroll
+    for (int s = 0; s < KH; ++s) {
+      const float2 v = (s < klim) ? arow[s] : make_float2(0.f, 0.f);
+      ar[s] = v.x;
+      ai[s] = v.y;
+    }
+  }
+
+  // Rows owned in the result layout, and the Jacobi preconditioner D^{-1}.
+  float dinv[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int i = w * 32 + d32_row(r, half);
+    float d = 0.f;
+    if (i < K) d = p.precond_none ? 1.f : Ab[(int64_t)i * p.lda + i].x;
+    dinv[r] = (i < K) ? 1.f / d : 0.f;
+  }
+
+  float xr[16], xim[16], rr[16], ri[16], pr[16], pim[16];
+  float rho = 0.f, bb = 0.f, rres = 0.f;
+  int it = 0, t0 = 0;
+  bool active = false, conv = false, brk = false;
+
+  constexpr int kVecPerArray = KT * 16 * 64;
+  float* stv = chunked ? p.st.vec + (int64_t)L * 6 * kVecPerArray : nullptr;
+  float* stc = chunked ? p.st.col + (int64_t)L * 8 * 32 : nullptr;
+
+  if (!chunked || p.first) {
+    const float2* Bb = p.B ? p.B + (int64_t)b * p.stride_b : nullptr;
+    float part[2] = {0.f, 0.f};
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int i = w * 32 + d32_row(r, half);
+      float2 bv = make_float2(0.f, 0.f);
+      if (i < K && jvalid) {
+        if (Bb)
+          bv = Bb[(int64_t)j * p.ldb + i];
+        else
+          bv = make_float2(i == j ? 1.f : 0.f, 0.f);
+      }
+      xr[r] = 0.f;
+      xim[r] = 0.f;
+      rr[r] = bv.x;
+      ri[r] = bv.y;
+      pr[r] = dinv[r] * bv.x;
+      pim[r] = dinv[r] * bv.y;
+      const float n2 = bv.x * bv.x + bv.y * bv.y;
+      part[0] += n2;
+      part[1] += dinv[r] * n2;
+    }
+    col_reduce<KT, 2>(part, red, w, jl, half);
+    bb = part[0];
+    rho = part[1];
+    rres = bb;
+    active = jvalid && bb > 0.f;
+    conv = true;  // reset below for columns that must iterate
+    if (active) conv = false;
+  } else {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int o = w * 16 * 64 + r * 64 + lane;
+      xr[r] = stv[0 * kVecPerArray + o];
+      xim[r] = stv[1 * kVecPerArray + o];
+      rr[r] = stv[2 * kVecPerArray + o];
+      ri[r] = stv[3 * kVecPerArray + o];
+      pr[r] = stv[4 * kVecPerArray + o];
+      pim[r] = stv[5 * kVecPerArray + o];
+    }
+    rho = stc[0 * 32 + jl];
+    bb = stc[1 * 32 + jl];
+    rres = stc[2 * 32 + jl];
+    it = (int)stc[3 * 32 + jl];
+    active = stc[4 * 32 + jl] != 0.f;
+    conv = stc[5 * 32 + jl] != 0.f;
+    brk = stc[6 * 32 + jl] != 0.f;
+    t0 = (int)stc[7 * 32 + 0];
+  }
+
+#pragma unroll
+  for (int r = 0; r < 16; ++r) Psh[w * 32 + d32_row(r, half)][jl] = make_float2(pr[r], pim[r]);
+
+  const float tol2 = p.tol * p.tol;
+  const int tend = chunked ? min(p.max_iter, t0 + p.chunk) : p.max_iter;
+  int t = t0;
+  while (t < tend) {
+    if (!__any(active)) break;  // identical in every wave: workgroup-uniform
+    ++t;
+    __syncthreads();  // P visible to all waves
+    floatx16 qr, qi;
+    apply_a<KT, AREG>(qr, qi, ar, ai, arow, klim, false, diag_s, Psh, half, jl);
+
+    float g[1] = {0.f};
+#pragma unroll
+    for (int r = 0; r < 16; ++r) g[0] += pr[r] * qr[r] + pim[r] * qi[r];
+    col_reduce<KT, 1>(g, red, w, jl, half);
+    const float gamma = g[0];
+    if (active) {
+      if (!isfinite(gamma) || gamma < 0.f) {
+        brk = true;  // A not numerically HPD
+        active = false;
+      } else if (gamma == 0.f) {
+        conv = true;  // p = 0: the residual underflowed to zero, nothing left to solve
+        active = false;
+      }
+    }
+    const float alpha = active ? rho / gamma : 0.f;
+    if (active) it = t;
+    float s2[2] = {0.f, 0.f};
+    if (active) {  // frozen columns keep x and r untouched (0 * NaN would not)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        xr[r] += alpha * pr[r];
+        xim[r] += alpha * pim[r];
+        rr[r] -= alpha * qr[r];
+        ri[r] -= alpha * qi[r];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const float n2 = rr[r] * rr[r] + ri[r] * ri[r];
+      s2[0] += n2;
+      s2[1] += dinv[r] * n2;
+    }
+    col_reduce<KT, 2>(s2, red + 1, w, jl, half);
+    if (active) {
+      rres = s2[0];
+      // Converged by the stop rule, or the residual underflowed: r^H D^{-1} r = 0
+      // with D > 0 only for r = 0 (and the next beta would be 0/0).
+      if (s2[0] <= tol2 * bb || s2[1] == 0.f) {
+        active = false;
+        conv = true;
+      }
+    }
+    if (active) {
+      const float beta = s2[1] / rho;
+      rho = s2[1];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        pr[r] = dinv[r] * rr[r] + beta * pr[r];
+        pim[r] = dinv[r] * ri[r] + beta * pim[r];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) Psh[w * 32 + d32_row(r, half)][jl] = make_float2(pr[r], pim[r]);
+  }
+
+  const bool finished = !__any(active) || t >= p.max_iter;
+  if (chunked && !finished) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int o = w * 16 * 64 + r * 64 + lane;
+      stv[0 * kVecPerArray + o] = xr[r];
+      stv[1 * kVecPerArray + o] = xim[r];
+      stv[2 * kVecPerArray + o] = rr[r];
+      stv[3 * kVecPerArray + o] = ri[r];
+      stv[4 * kVecPerArray + o] = pr[r];
+      stv[5 * kVecPerArray + o] = pim[r];
+    }
+    if (w == 0 && half == 0) {
+      stc[0 * 32 + jl] = rho;
+      stc[1 * 32 + jl] = bb;
+      stc[2 * 32 + jl] = rres;
+      stc[3 * 32 + jl] = (float)it;
+      stc[4 * 32 + jl] = active ? 1.f : 0.f;
+      stc[5 * 32 + jl] = conv ? 1.f : 0.f;
+      stc[6 * 32 + jl] = brk ? 1.f : 0.f;
+      if (jl == 0) stc[7 * 32 + 0] = (float)t;
+    }
+    if (threadIdx.x == 0) p.st.done[L] = 0;
+    return;
+  }
+
+  // ---- final outputs --------------------------------------------------------
+  float2* Xb = p.X + (int64_t)b * p.stride_x;
+  if (jvalid) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int i = w * 32 + d32_row(r, half);
+      if (i < K) Xb[(int64_t)j * p.ldx + i] = make_float2(xr[r], xim[r]);
+    }
+  }
+  int col_status = kStatusOk;
+  if (brk)
+    col_status = kStatusBreakdown;
+  else if (p.tol > 0.f && !conv)
+    col_status = kStatusNotConverged;
+  if (w == 0 && half == 0 && jvalid) {
+    if (p.iters) p.iters[(int64_t)b * p.nrhs + j] = it;
+    if (p.relres) p.relres[(int64_t)b * p.nrhs + j] = bb > 0.f ? sqrtf(rres / bb) : 0.f;
+  }
+  if (p.wg_status) {
+    const bool anyb = __any(brk);
+    const bool anyn = __any(col_status == kStatusNotConverged);
+    if (threadIdx.x == 0) p.wg_status[L] = anyb ? kStatusBreakdown : (anyn ? kStatusNotConverged : kStatusOk);
+  }
+
+  if (p.gdiag) {
+    // ||H X||^2 contribution of this block: x_j^H (A - diag(A) + diag(H^H H)) x_j.
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 16; ++r) Psh[w * 32 + d32_row(r, half)][jl] = make_float2(xr[r], xim[r]);
+    __syncthreads();
+    floatx16 yr, yi;
+    apply_a<KT, AREG>(yr, yi, ar, ai, arow, klim, true, diag_s, Psh, half, jl);
+    float q[1] = {0.f};
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int i = w * 32 + d32_row(r, half);
+      const float gd = (i < K) ? p.gdiag[(int64_t)b * K + i] : 0.f;
+      q[0] += xr[r] * yr[r] + xim[r] * yi[r] + gd * (xr[r] * xr[r] + xim[r] * xim[r]);
+    }
+    col_reduce<KT, 1>(q, red, w, jl, half);
+    __shared__ float colsum[32];
+    if (w == 0 && half == 0) colsum[jl] = q[0];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      float s = 0.f;
+      for (int c = 0; c < 32; ++c) s += colsum[c];
+      p.fpart[L] = s;
+    }
+  }
+  if (chunked && threadIdx.x == 0) p.st.done[L] = 1;
+}
+
+__global__ void status_reduce_kernel(const int32_t* __restrict__ wg, int ncb, int batch, int32_t* __restrict__ out) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= batch) return;
+  int s = kStatusOk;
+  for (int c = 0; c < ncb; ++c) {
+    const int v = wg[(int64_t)b * ncb + c];
+    if (v == kStatusBreakdown) s = kStatusBreakdown;
+    else if (v == kStatusNotConverged && s == kStatusOk) s = kStatusNotConverged;
+  }
+  out[b] = s;
+}
+
+template <int KT, bool AREG>
+hipError_t launch_kt(const PcgLaunch& p, int grid, hipStream_t s) {
+  hipLaunchKernelGGL((pcg_f32_kernel<KT, AREG>), dim3(grid), dim3(KT * 64), 0, s, p);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+int pcg_workgroups(int batch, int K, int nrhs) {
+  (void)K;
+  return batch * ((nrhs + 31) / 32);
+}
+
+size_t pcg_state_floats_per_wg(int K) {
+  const int kt = (K + 31) / 32;
+  return (size_t)6 * kt * 16 * 64;
+}
+
+hipError_t launch_pcg(const PcgLaunch& p, hipStream_t s, int* wg_count_out) {
+  const int grid = pcg_workgroups(p.batch, p.K, p.nrhs);
+  if (wg_count_out) *wg_count_out = grid;
+  if (grid == 0) return hipSuccess;
+  const int kt = (p.K + 31) / 32;
+  switch (kt) {
+    case 1: return launch_kt<1, true>(p, grid, s);
+    case 2: return launch_kt<2, true>(p, grid, s);
+    case 3: return launch_kt<3, false>(p, grid, s);
+    case 4: return launch_kt<4, false>(p, grid, s);
+    case 5: return launch_kt<5, false>(p, grid, s);
+    case 6: return launch_kt<6, false>(p, grid, s);
+    case 7: return launch_kt<7, false>(p, grid, s);
+    case 8: return launch_kt<8, false>(p, grid, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_status_reduce(const int32_t* wg_status, int ncb, int batch, int32_t* status, hipStream_t s) {
+  if (batch == 0) return hipSuccess;
+  hipLaunchKernelGGL(status_reduce_kernel, dim3((batch + 255) / 256), dim3(256), 0, s, wg_status, ncb, batch,
+                     status);
+  return hipGetLastError();
+}
+
+}  // namespace jacpcg

@@ -1,0 +1,349 @@
+// Session runtime: workspace arena, timing events and the composed paths
+// (batched persistent path and the plain one-instance-at-a-time path).
+#include "session.hpp"
+
+#include <algorithm>
+#include <cstring>
+
+using namespace jacpcg;
+
+namespace {
+
+int hip_error(jacpcg_session* s, hipError_t e, const char* what) {
+  s->poisoned = true;
+  std::string m = std::string(what) + ": " + hipGetErrorString(e);
+  return set_error(JACPCG_E_HIP, m.c_str());
+}
+
+#define S_HIP(expr)                                       \
+  do {                                                    \
+    hipError_t e_ = (expr);                               \
+    if (e_ != hipSuccess) return hip_error(this, e_, #expr); \
+  } while (0)
+
+}  // namespace
+
+int jacpcg_session::reserve(const Workspace& ws) {
+  if (ws.bytes <= arena_bytes) return JACPCG_OK;
+  if (budget && ws.bytes > budget) return set_error(JACPCG_E_OUT_OF_MEMORY, "workspace exceeds the session budget");
+  // Work already enqueued may still use the old arena.
+  S_HIP(hipDeviceSynchronize());
+  if (arena) S_HIP(hipFree(arena));
+  arena = nullptr;
+  arena_bytes = 0;
+  const size_t want = std::max(ws.bytes, (size_t)1 << 20);
+  hipError_t e = hipMalloc((void**)&arena, want);
+  if (e != hipSuccess) {
+    arena = nullptr;
+    (void)hipGetLastError();
+    return set_error(JACPCG_E_OUT_OF_MEMORY, "hipMalloc of the workspace failed");
+  }
+  arena_bytes = want;
+  return JACPCG_OK;
+}
+
+void* jacpcg_session::host_scratch(size_t bytes) {
+  if (bytes <= pinned_bytes) return pinned;
+  if (pinned) (void)hipHostFree(pinned);
+  pinned = nullptr;
+  pinned_bytes = 0;
+  const size_t want = std::max(bytes, (size_t)1 << 16);
+  if (hipHostMalloc(&pinned, want, hipHostMallocDefault) != hipSuccess) {
+    pinned = nullptr;
+    return nullptr;
+  }
+  pinned_bytes = want;
+  return pinned;
+}
+
+hipEvent_t jacpcg_session::get_event() {
+  if (!event_pool.empty()) {
+    hipEvent_t e = event_pool.back();
+    event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  (void)hipEventCreate(&e);
+  return e;
+}
+
+hipError_t jacpcg_session::collect_events() {
+  for (auto& p : pending) {
+    hipError_t e = hipEventSynchronize(p.b);
+    if (e != hipSuccess) return e;
+    float ms = 0.f;
+    e = hipEventElapsedTime(&ms, p.a, p.b);
+    if (e != hipSuccess) return e;
+    phase_ms[p.phase] += ms;
+    phase_count[p.phase] += 1;
+    event_pool.push_back(p.a);
+    event_pool.push_back(p.b);
+  }
+  pending.clear();
+  return hipSuccess;
+}
+
+void jacpcg_session::shutdown() {
+  (void)hipDeviceSynchronize();
+  for (auto& p : pending) {
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  pending.clear();
+  for (auto e : event_pool) (void)hipEventDestroy(e);
+  event_pool.clear();
+  if (arena) (void)hipFree(arena);
+  arena = nullptr;
+  if (pinned) (void)hipHostFree(pinned);
+  pinned = nullptr;
+  if (!tune_path.empty()) tuner.save(tune_path);
+}
+
+// ---------------------------------------------------------------------------
+// Batched path: Gram -> persistent PCG (+ ||H X||^2 pass) -> precoder.
+// ---------------------------------------------------------------------------
+int jacpcg_session::run_rzf(hipStream_t st, int batch, int M, int K, const float2* H, int64_t ldh, int64_t stride_h,
+                            double xi, double power, double tol, int max_iter, int gram_prec, bool refine,
+                            bool precond_none, double refine_tol, float2* W, int64_t ldw, int64_t stride_w,
+                            float2* X_out, double2* X64_out, jacpcg_stats* stats) {
+  (void)refine_tol;
+  if (refine) return set_error(JACPCG_E_UNSUPPORTED, "FP64 refinement not available in this build");
+  const int ncb = (K + 31) / 32;
+  const size_t KK = (size_t)K * K;
+  Workspace ws;
+  const size_t oA = ws.take<float2>(batch * KK);
+  const size_t oG = ws.take<float>((size_t)batch * K);
+  const size_t oX = X_out ? 0 : ws.take<float2>(batch * KK);
+  const size_t oF = ws.take<float>((size_t)batch * ncb);
+  const size_t oWG = ws.take<int32_t>((size_t)batch * ncb);
+  const size_t oS = ws.take<int32_t>(batch);
+  const size_t oI = ws.take<int32_t>((size_t)batch * K);
+  const size_t oR = ws.take<float>((size_t)batch * K);
+  const size_t oB = ws.take<float>(batch);
+  const size_t oX64 = X64_out ? 0 : 0;
+  (void)oX64;
+  if (int rc = reserve(ws)) return rc;
+  float2* A = at<float2>(oA);
+  float* gdiag = at<float>(oG);
+  float2* X = X_out ? X_out : at<float2>(oX);
+  float* fpart = at<float>(oF);
+  int32_t* wgs = at<int32_t>(oWG);
+  int32_t* status = at<int32_t>(oS);
+  int32_t* iters = at<int32_t>(oI);
+  float* relres = at<float>(oR);
+  float* beta = at<float>(oB);
+
+  GramLaunch g{};
+  g.H = H;
+  g.ldh = ldh;
+  g.stride_h = stride_h;
+  g.batch = batch;
+  g.M = M;
+  g.K = K;
+  g.xi = (float)xi;
+  g.A = A;
+  g.lda = K;
+  g.stride_a = (int64_t)KK;
+  g.diag = nullptr;
+  g.gdiag = gdiag;
+  g.precision = gram_prec;
+  g.m_split = tuner.gram_waves(M, K, gram_prec);
+  hipError_t e = timed(st, JACPCG_PHASE_GRAM, [&] { return launch_gram(g, st); });
+  if (e == hipErrorNotSupported) return set_error(JACPCG_E_UNSUPPORTED, "Gram precision not available");
+  if (e != hipSuccess) return hip_error(this, e, "gram launch");
+
+  PcgLaunch p{};
+  p.A = A;
+  p.lda = K;
+  p.stride_a = (int64_t)KK;
+  p.B = nullptr;
+  p.X = X;
+  p.ldx = K;
+  p.stride_x = (int64_t)KK;
+  p.batch = batch;
+  p.K = K;
+  p.nrhs = K;
+  p.tol = (float)tol;
+  p.max_iter = max_iter;
+  p.precond_none = precond_none;
+  p.iters = iters;
+  p.relres = relres;
+  p.wg_status = wgs;
+  p.gdiag = gdiag;
+  p.fpart = fpart;
+  e = timed(st, JACPCG_PHASE_SOLVE, [&] { return launch_pcg(p, st, nullptr); });
+  if (e != hipSuccess) return hip_error(this, e, "pcg launch");
+  e = launch_status_reduce(wgs, ncb, batch, status, st);
+  if (e != hipSuccess) return hip_error(this, e, "status reduce launch");
+
+  PrecoderLaunch E{};
+  E.H = H;
+  E.ldh = ldh;
+  E.stride_h = stride_h;
+  E.X = X;
+  E.ldx = K;
+  E.stride_x = (int64_t)KK;
+  E.W = W;
+  E.ldw = ldw;
+  E.stride_w = stride_w;
+  E.batch = batch;
+  E.M = M;
+  E.K = K;
+  E.nrhs = K;
+  E.fpart = fpart;
+  E.ncb = ncb;
+  E.power = (float)power;
+  E.beta_out = beta;
+  e = timed(st, JACPCG_PHASE_EPILOGUE, [&] { return launch_precoder(E, st); });
+  if (e != hipSuccess) return hip_error(this, e, "precoder launch");
+
+  if (X64_out) {
+    e = launch_widen(X, K, (int64_t)KK, batch, K, K, X64_out, st);
+    if (e != hipSuccess) return hip_error(this, e, "widen launch");
+  }
+
+  if (!stats) return JACPCG_OK;
+  const size_t hb = (size_t)batch * K * 8 + (size_t)batch * 8;
+  char* h = (char*)host_scratch(hb);
+  if (!h) return set_error(JACPCG_E_OUT_OF_MEMORY, "pinned host staging allocation failed");
+  int32_t* h_it = (int32_t*)h;
+  float* h_rr = (float*)(h_it + (size_t)batch * K);
+  int32_t* h_st = (int32_t*)(h_rr + (size_t)batch * K);
+  float* h_b = (float*)(h_st + batch);
+  S_HIP(hipMemcpyAsync(h_it, iters, (size_t)batch * K * 4, hipMemcpyDeviceToHost, st));
+  S_HIP(hipMemcpyAsync(h_rr, relres, (size_t)batch * K * 4, hipMemcpyDeviceToHost, st));
+  S_HIP(hipMemcpyAsync(h_st, status, (size_t)batch * 4, hipMemcpyDeviceToHost, st));
+  S_HIP(hipMemcpyAsync(h_b, beta, (size_t)batch * 4, hipMemcpyDeviceToHost, st));
+  S_HIP(hipStreamSynchronize(st));
+  fill_stats_host(stats, batch, K, h_it, h_rr, h_st, h_b);
+  return stats->worst_status;
+}
+
+// ---------------------------------------------------------------------------
+// Plain path: one instance at a time, one launch per PCG iteration.
+// ---------------------------------------------------------------------------
+int jacpcg_session::run_rzf_plain(hipStream_t st, int batch, int M, int K, const float2* H, int64_t ldh,
+                                  int64_t stride_h, double xi, double power, double tol, int max_iter,
+                                  bool precond_none, float2* W, int64_t ldw, int64_t stride_w, float2* X_out,
+                                  jacpcg_stats* stats) {
+  const int ncb = (K + 31) / 32;
+  const size_t KK = (size_t)K * K;
+  Workspace ws;
+  const size_t oA = ws.take<float2>(KK);
+  const size_t oG = ws.take<float>(K);
+  const size_t oX = X_out ? 0 : ws.take<float2>(batch * KK);
+  const size_t oF = ws.take<float>(ncb);
+  const size_t oWG = ws.take<int32_t>(ncb);
+  const size_t oS = ws.take<int32_t>(batch);
+  const size_t oI = ws.take<int32_t>((size_t)batch * K);
+  const size_t oR = ws.take<float>((size_t)batch * K);
+  const size_t oB = ws.take<float>(batch);
+  const size_t oSV = ws.take<float>(pcg_state_floats_per_wg(K) * ncb);
+  const size_t oSC = ws.take<float>((size_t)8 * 32 * ncb);
+  const size_t oSD = ws.take<int32_t>(ncb);
+  if (int rc = reserve(ws)) return rc;
+  float2* A = at<float2>(oA);
+  float* gdiag = at<float>(oG);
+  float2* X = X_out ? X_out : at<float2>(oX);
+  float* fpart = at<float>(oF);
+  int32_t* wgs = at<int32_t>(oWG);
+  int32_t* status = at<int32_t>(oS);
+  int32_t* iters = at<int32_t>(oI);
+  float* relres = at<float>(oR);
+  float* beta = at<float>(oB);
+  PcgState state{at<float>(oSV), at<float>(oSC), at<int32_t>(oSD)};
+  int32_t* h_done = (int32_t*)host_scratch(std::max<size_t>((size_t)ncb * 4, (size_t)batch * K * 8 + batch * 8));
+  if (!h_done) return set_error(JACPCG_E_OUT_OF_MEMORY, "pinned host staging allocation failed");
+
+  for (int b = 0; b < batch; ++b) {
+    const float2* Hb = H + (int64_t)b * stride_h;
+    GramLaunch g{};
+    g.H = Hb;
+    g.ldh = ldh;
+    g.stride_h = 0;
+    g.batch = 1;
+    g.M = M;
+    g.K = K;
+    g.xi = (float)xi;
+    g.A = A;
+    g.lda = K;
+    g.stride_a = (int64_t)KK;
+    g.gdiag = gdiag;
+    g.precision = 0;
+    g.m_split = tuner.gram_waves(M, K, 0);
+    hipError_t e = timed(st, JACPCG_PHASE_GRAM, [&] { return launch_gram(g, st); });
+    if (e != hipSuccess) return hip_error(this, e, "gram launch");
+
+    PcgLaunch p{};
+    p.A = A;
+    p.lda = K;
+    p.stride_a = (int64_t)KK;
+    p.X = X + (int64_t)b * KK;
+    p.ldx = K;
+    p.stride_x = (int64_t)KK;
+    p.batch = 1;
+    p.K = K;
+    p.nrhs = K;
+    p.tol = (float)tol;
+    p.max_iter = max_iter;
+    p.precond_none = precond_none;
+    p.iters = iters + (int64_t)b * K;
+    p.relres = relres + (int64_t)b * K;
+    p.wg_status = wgs;
+    p.gdiag = gdiag;
+    p.fpart = fpart;
+    p.st = state;
+    p.chunk = 1;
+    const int launches = std::max(1, max_iter);
+    for (int t = 0; t < launches; ++t) {
+      p.first = (t == 0);
+      e = timed(st, JACPCG_PHASE_SOLVE, [&] { return launch_pcg(p, st, nullptr); });
+      if (e != hipSuccess) return hip_error(this, e, "pcg launch");
+      if (tol > 0.0 && t + 1 < launches) {
+        // Host-driven convergence test after every iteration.
+        S_HIP(hipMemcpyAsync(h_done, state.done, (size_t)ncb * 4, hipMemcpyDeviceToHost, st));
+        S_HIP(hipStreamSynchronize(st));
+        bool all = true;
+        for (int c = 0; c < ncb; ++c) all = all && h_done[c] != 0;
+        if (all) break;
+      }
+    }
+    e = launch_status_reduce(wgs, ncb, 1, status + b, st);
+    if (e != hipSuccess) return hip_error(this, e, "status reduce launch");
+
+    PrecoderLaunch E{};
+    E.H = Hb;
+    E.ldh = ldh;
+    E.stride_h = 0;
+    E.X = X + (int64_t)b * KK;
+    E.ldx = K;
+    E.stride_x = (int64_t)KK;
+    E.W = W + (int64_t)b * stride_w;
+    E.ldw = ldw;
+    E.stride_w = 0;
+    E.batch = 1;
+    E.M = M;
+    E.K = K;
+    E.nrhs = K;
+    E.fpart = fpart;
+    E.ncb = ncb;
+    E.power = (float)power;
+    E.beta_out = beta + b;
+    e = timed(st, JACPCG_PHASE_EPILOGUE, [&] { return launch_precoder(E, st); });
+    if (e != hipSuccess) return hip_error(this, e, "precoder launch");
+  }
+
+  if (!stats) return JACPCG_OK;
+  char* h = (char*)h_done;
+  int32_t* h_it = (int32_t*)h;
+  float* h_rr = (float*)(h_it + (size_t)batch * K);
+  int32_t* h_st = (int32_t*)(h_rr + (size_t)batch * K);
+  float* h_b = (float*)(h_st + batch);
+  S_HIP(hipMemcpyAsync(h_it, iters, (size_t)batch * K * 4, hipMemcpyDeviceToHost, st));
+  S_HIP(hipMemcpyAsync(h_rr, relres, (size_t)batch * K * 4, hipMemcpyDeviceToHost, st));
+  S_HIP(hipMemcpyAsync(h_st, status, (size_t)batch * 4, hipMemcpyDeviceToHost, st));
+  S_HIP(hipMemcpyAsync(h_b, beta, (size_t)batch * 4, hipMemcpyDeviceToHost, st));
+  S_HIP(hipStreamSynchronize(st));
+  fill_stats_host(stats, batch, K, h_it, h_rr, h_st, h_b);
+  return stats->worst_status;
+}

@@ -1,0 +1,88 @@
+// Session state of libjacpcg: device, workspace arena, pinned staging memory,
+// per-phase kernel timing and the autotuned launch choices.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/jacpcg.h"
+#include "common.hpp"
+#include "tuner.hpp"
+
+namespace jacpcg {
+
+// Two-phase workspace plan: offsets are taken first, the arena is sized once,
+// then offsets become device pointers.
+struct Workspace {
+  size_t bytes = 0;
+  template <class T>
+  size_t take(size_t n) {
+    const size_t off = (bytes + 255) & ~size_t(255);
+    bytes = off + n * sizeof(T);
+    return off;
+  }
+};
+
+int set_error(int code, const char* msg);
+void fill_stats_host(jacpcg_stats* st, int batch, int K, const int32_t* iters, const float* relres,
+                     const int32_t* status, const float* beta);
+
+}  // namespace jacpcg
+
+struct jacpcg_session {
+  int device = 0;
+  size_t budget = 0;
+  std::string tune_path;
+  jacpcg::Tuner tuner;
+  bool poisoned = false;
+  bool profiling = false;
+
+  char* arena = nullptr;
+  size_t arena_bytes = 0;
+  void* pinned = nullptr;
+  size_t pinned_bytes = 0;
+
+  struct PendingEvent {
+    hipEvent_t a, b;
+    int phase;
+  };
+  std::vector<PendingEvent> pending;
+  std::vector<hipEvent_t> event_pool;
+  double phase_ms[JACPCG_NUM_PHASES] = {};
+  int64_t phase_count[JACPCG_NUM_PHASES] = {};
+
+  // Grow the arena to hold `ws` (synchronises the device when it has to grow).
+  int reserve(const jacpcg::Workspace& ws);
+  template <class T>
+  T* at(size_t off) {
+    return reinterpret_cast<T*>(arena + off);
+  }
+  // Pinned host staging buffer of at least `bytes`.
+  void* host_scratch(size_t bytes);
+
+  hipEvent_t get_event();
+  template <class F>
+  hipError_t timed(hipStream_t st, int phase, F&& launch) {
+    if (!profiling) return launch();
+    hipEvent_t a = get_event(), b = get_event();
+    hipError_t e = hipEventRecord(a, st);
+    if (e != hipSuccess) return e;
+    e = launch();
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(b, st);
+    pending.push_back({a, b, phase});
+    return e;
+  }
+  hipError_t collect_events();
+  void shutdown();
+
+  int run_rzf(hipStream_t st, int batch, int M, int K, const float2* H, int64_t ldh, int64_t stride_h, double xi,
+              double power, double tol, int max_iter, int gram_prec, bool refine, bool precond_none,
+              double refine_tol, float2* W, int64_t ldw, int64_t stride_w, float2* X_out, double2* X64_out,
+              jacpcg_stats* stats);
+  int run_rzf_plain(hipStream_t st, int batch, int M, int K, const float2* H, int64_t ldh, int64_t stride_h,
+                    double xi, double power, double tol, int max_iter, bool precond_none, float2* W, int64_t ldw,
+                    int64_t stride_w, float2* X_out, jacpcg_stats* stats);
+};

@@ -1,0 +1,125 @@
+"""The C ABI loads, exports every declared symbol and rejects bad arguments on
+the host, before any device work (runs without a GPU)."""
+
+import ctypes as C
+import subprocess
+
+import pytest
+
+from paper_2305_13925_amd import binding as bd
+
+L = bd.lib()
+NULL = None
+FAKE = C.c_void_p(0x1000)      # never dereferenced: validation fails first
+
+
+def _err():
+    return bd.last_error()
+
+
+def test_exports_every_declared_symbol():
+    declared = bd.exported_symbols()
+    assert {"jacpcg_gram", "jacpcg_solve", "rzf_precoder", "rzf_precoder_plain",
+            "jacpcg_session_create", "jacpcg_session_destroy"} <= set(declared)
+    out = subprocess.run(["nm", "-D", "--defined-only", bd.LIB_PATH], capture_output=True, text=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if " T " in line}
+    missing = [s for s in declared if s not in exported]
+    assert not missing, missing
+    for s in declared:
+        assert hasattr(L, s)
+
+
+def test_version_and_status_strings():
+    assert L.jacpcg_version() >= 10000
+    for code in (0, 1, 2, -1, -2, -3, -4, -5, -6, -7, -8, -9):
+        assert bd.status_string(code) != "unknown status"
+    assert bd.status_string(12345) == "unknown status"
+
+
+def test_session_create_argument_errors():
+    h = C.c_void_p()
+    assert L.jacpcg_session_create(0, 0, None, None) == bd.E_INVALID_ARG
+    assert L.jacpcg_session_create(-1, 0, None, C.byref(h)) == bd.E_INVALID_ARG
+    assert "device" in _err()
+
+
+def _gram(**kw):
+    a = dict(s=NULL, stream=NULL, batch=2, M=64, K=16, H=FAKE, ldh=64, sh=64 * 16, xi=1.0, prec=0,
+             A=FAKE, lda=16, sa=256, diag=NULL)
+    a.update(kw)
+    return L.jacpcg_gram(a["s"], a["stream"], a["batch"], a["M"], a["K"], a["H"], a["ldh"], a["sh"], a["xi"],
+                         a["prec"], a["A"], a["lda"], a["sa"], a["diag"])
+
+
+@pytest.mark.parametrize("kw,word", [
+    (dict(K=0), "K"), (dict(K=257), "K"), (dict(M=0), "M"), (dict(batch=-1), "batch"),
+    (dict(xi=-1.0), "xi"), (dict(xi=float("nan")), "xi"), (dict(ldh=63), "ldh"),
+    (dict(sh=64 * 16 - 1), "stride_h"), (dict(H=NULL), "H"), (dict(A=NULL), "A"), (dict(lda=15), "lda"),
+])
+def test_gram_validation(kw, word):
+    assert _gram(**kw) == bd.E_INVALID_ARG
+    assert word in _err()
+
+
+def test_gram_unsupported_precision_and_null_session():
+    assert _gram(prec=7) == bd.E_UNSUPPORTED
+    assert _gram() == bd.E_INVALID_ARG
+    assert "session" in _err()
+    assert _gram(batch=0, s=NULL) == bd.E_INVALID_ARG   # valid sizes, still needs a session
+
+
+def _solve(**kw):
+    a = dict(s=NULL, batch=1, K=8, n=8, A=FAKE, lda=8, sa=64, B=NULL, ldb=8, sb=64, X=FAKE, ldx=8, sx=64,
+             tol=0.0, it=4, flags=0)
+    a.update(kw)
+    return L.jacpcg_solve(a["s"], NULL, a["batch"], a["K"], a["n"], a["A"], a["lda"], a["sa"], a["B"], a["ldb"],
+                          a["sb"], a["X"], a["ldx"], a["sx"], a["tol"], a["it"], a["flags"], NULL, NULL, NULL)
+
+
+@pytest.mark.parametrize("kw,word", [
+    (dict(n=5), "nrhs"), (dict(n=0), "nrhs"), (dict(n=300, B=FAKE), "nrhs"), (dict(tol=-1e-3), "tol"),
+    (dict(it=-1), "max_iter"), (dict(flags=9), "flags"), (dict(lda=7), "lda"), (dict(ldx=3), "ldx"),
+    (dict(B=FAKE, ldb=2), "ldb"), (dict(A=NULL), "A"), (dict(X=NULL), "X"), (dict(K=0), "K"),
+    (dict(batch=2, sx=10), "stride_x"),
+])
+def test_solve_validation(kw, word):
+    assert _solve(**kw) == bd.E_INVALID_ARG
+    assert word in _err()
+
+
+def _rzf(**kw):
+    a = dict(batch=1, M=32, K=4, H=FAKE, ldh=32, sh=128, xi=0.5, power=1.0, tol=0.0, it=4, prec=0, flags=0,
+             rtol=1e-10, W=FAKE, ldw=32, sw=128)
+    a.update(kw)
+    return L.rzf_precoder(NULL, NULL, a["batch"], a["M"], a["K"], a["H"], a["ldh"], a["sh"], a["xi"], a["power"],
+                          a["tol"], a["it"], a["prec"], a["flags"], a["rtol"], a["W"], a["ldw"], a["sw"], NULL, NULL,
+                          NULL)
+
+
+@pytest.mark.parametrize("kw,word", [
+    (dict(power=0.0), "power"), (dict(power=-2.0), "power"), (dict(W=NULL), "W"), (dict(ldw=31), "ldw"),
+    (dict(tol=-1.0), "tol"), (dict(it=-3), "max_iter"), (dict(rtol=-1.0), "refine_tol"),
+    (dict(xi=float("inf")), "xi"), (dict(flags=5), "flags"),
+])
+def test_rzf_validation(kw, word):
+    assert _rzf(**kw) == bd.E_INVALID_ARG
+    assert word in _err()
+
+
+def test_rzf_unknown_precision():
+    assert _rzf(prec=0x7) == bd.E_UNSUPPORTED
+    assert _rzf(prec=0x1000) == bd.E_UNSUPPORTED
+
+
+def test_plain_validation():
+    rc = L.rzf_precoder_plain(NULL, NULL, 1, 32, 300, FAKE, 32, 0, 0.5, 1.0, 0.0, 4, 0, FAKE, 32, 0, NULL, NULL)
+    assert rc == bd.E_INVALID_ARG and "K" in _err()
+
+
+def test_binding_fails_loudly_without_device():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(bd.JacpcgError) as ei:
+        bd.Session(0)
+    assert ei.value.code == bd.E_NO_DEVICE

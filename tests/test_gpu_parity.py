@@ -1,0 +1,280 @@
+"""GPU path (libjacpcg through its C ABI) against the complex128 oracle.
+
+Bar (relative Frobenius error per instance): 1e-5 for every FP32 result. FP32
+fixed-iteration results are compared with the oracle at the same iteration
+count; tolerance-stopped results with the oracle replaying each column for the
+GPU's reported iteration count. The error against the exact (FP64 direct
+inverse) precoder is printed for every case.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+from channelgen import channel_batch, workload
+from paper_2305_13925_amd import binding as bd
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "GPU tests need a HIP device"
+    return t
+
+
+@pytest.fixture(scope="module")
+def sess(torch):
+    s = bd.Session(0)
+    yield s
+    s.close()
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def dev(torch, x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
+
+
+def crandn(rng, *shape):
+    return ((rng.standard_normal(shape) + 1j * rng.standard_normal(shape)) / np.sqrt(2)).astype(np.complex64)
+
+
+def chan(rng, batch, K, M, spread=10.0):
+    """Random channel [batch, K, M] with per-user gains spanning `spread`."""
+    g = np.geomspace(1.0, spread, K).astype(np.float32)
+    return (crandn(rng, batch, K, M) * g[None, :, None]).astype(np.complex64)
+
+
+# ---------------------------------------------------------------------------
+GRAM_SHAPES = [(256, 16, 1), (100, 37, 3), (1024, 64, 4), (333, 70, 2), (64, 256, 1), (1000, 130, 2),
+               (7, 5, 3), (64, 1, 2), (4100, 96, 1)]
+
+
+@pytest.mark.parametrize("M,K,batch", GRAM_SHAPES)
+def test_gram_parity(torch, sess, M, K, batch):
+    rng = np.random.default_rng(M * 1000 + K)
+    H = chan(rng, batch, K, M)
+    xi = 0.37
+    diag = torch.empty((batch, K), dtype=torch.float32, device="cuda")
+    A = bd.jacpcg_gram(sess, dev(torch, H), xi, diag=diag)
+    torch.cuda.synchronize()
+    A = A.cpu().numpy().astype(np.complex128)
+    d = diag.cpu().numpy()
+    for b in range(batch):
+        ref = oracle.gram(H[b].T, xi)
+        assert rel(A[b], ref) <= TOL, (b, rel(A[b], ref))
+        assert np.array_equal(A[b], A[b].conj().T)          # exactly Hermitian
+        assert np.all(A[b].diagonal().imag == 0)
+        np.testing.assert_array_equal(d[b], A[b].diagonal().real.astype(np.float32))
+
+
+def test_gram_batch_zero_is_noop(torch, sess):
+    H = torch.zeros((0, 4, 8), dtype=torch.complex64, device="cuda")
+    A = bd.jacpcg_gram(sess, H, 1.0)
+    assert A.shape == (0, 4, 4)
+
+
+# ---------------------------------------------------------------------------
+def _system(rng, batch, K, M, xi, spread=10.0):
+    H = chan(rng, batch, K, M, spread)
+    A64 = np.stack([oracle.gram(H[b].T, xi) for b in range(batch)])
+    return A64.astype(np.complex64)
+
+
+SOLVE_CASES = [(16, 16, 16, 2, True), (37, 37, 10, 2, True), (64, 64, 8, 3, True), (64, 20, 8, 2, False),
+               (100, 100, 12, 1, True), (130, 40, 10, 1, False), (256, 256, 6, 1, True), (5, 3, 5, 2, False),
+               (1, 1, 3, 2, True), (200, 33, 7, 2, False)]
+
+
+@pytest.mark.parametrize("K,n,T,batch,identity", SOLVE_CASES)
+def test_solve_fixed_iterations(torch, sess, K, n, T, batch, identity):
+    rng = np.random.default_rng(K * 100 + n)
+    A = _system(rng, batch, K, 2 * K + 7, xi=0.3)
+    B = None if identity else crandn(rng, batch, n, K)
+    iters = torch.empty((batch, n), dtype=torch.int32, device="cuda")
+    relres = torch.empty((batch, n), dtype=torch.float32, device="cuda")
+    status = torch.empty((batch,), dtype=torch.int32, device="cuda")
+    X = bd.jacpcg_solve(sess, dev(torch, A), None if B is None else dev(torch, B), tol=0.0, max_iter=T,
+                        iters=iters, relres=relres, status=status)
+    torch.cuda.synchronize()
+    X = X.cpu().numpy()
+    it, rr = iters.cpu().numpy(), relres.cpu().numpy()
+    # exactly T iterations, unless the FP32 residual became exactly zero (stop rule ||r|| <= 0)
+    assert np.all((it == T) | ((it < T) & (rr == 0.0)))
+    assert np.all(status.cpu().numpy() == bd.OK)
+    for b in range(batch):
+        Bm = None if B is None else B[b].T.astype(np.complex128)
+        ref = oracle.jacpcg(A[b].astype(np.complex128), Bm, tol=0.0, max_iter=T)
+        assert rel(X[b].T, ref["X"]) <= TOL, (b, rel(X[b].T, ref["X"]))
+        # recurrence residual: equal where it is above the FP32 rounding floor
+        np.testing.assert_allclose(relres.cpu().numpy()[b], ref["relres"], rtol=1e-2, atol=5e-5)
+
+
+@pytest.mark.parametrize("K,snr_spread", [(64, 30.0), (128, 10.0), (32, 100.0)])
+def test_solve_tolerance_replay(torch, sess, K, snr_spread):
+    rng = np.random.default_rng(K + 7)
+    batch, tol = 2, 1e-5
+    A = _system(rng, batch, K, 4 * K, xi=0.05, spread=snr_spread)
+    iters = torch.empty((batch, K), dtype=torch.int32, device="cuda")
+    relres = torch.empty((batch, K), dtype=torch.float32, device="cuda")
+    status = torch.empty((batch,), dtype=torch.int32, device="cuda")
+    X = bd.jacpcg_solve(sess, dev(torch, A), None, tol=tol, max_iter=500, iters=iters, relres=relres,
+                        status=status)
+    torch.cuda.synchronize()
+    X, it, rr = X.cpu().numpy(), iters.cpu().numpy(), relres.cpu().numpy()
+    assert np.all(status.cpu().numpy() == bd.OK)
+    assert np.all(rr <= tol)
+    for b in range(batch):
+        Ab = A[b].astype(np.complex128)
+        cols = []
+        for j in range(K):
+            cols.append(oracle.jacpcg(Ab, np.eye(K)[:, j], tol=0.0, max_iter=int(it[b, j]))["X"][:, 0])
+        ref = np.stack(cols, axis=1)
+        assert rel(X[b].T, ref) <= TOL, (b, rel(X[b].T, ref))
+        own = oracle.jacpcg(Ab, None, tol=tol, max_iter=500)["iters"]
+        assert np.max(np.abs(own - it[b])) <= 1
+
+
+def test_solve_breakdown_zero_column_and_plain_cg(torch, sess):
+    K = 8
+    bad = np.eye(K, dtype=np.complex64)
+    bad[0, 1] = bad[1, 0] = 3.0                                   # indefinite
+    Bm = np.zeros((1, 2, K), np.complex64)
+    Bm[0, 1, 0], Bm[0, 1, 1] = 1.0, -1.0
+    status = torch.empty((1,), dtype=torch.int32, device="cuda")
+    iters = torch.empty((1, 2), dtype=torch.int32, device="cuda")
+    X = bd.jacpcg_solve(sess, dev(torch, bad[None]), dev(torch, Bm), tol=0.0, max_iter=4, iters=iters,
+                        status=status)
+    torch.cuda.synchronize()
+    ref = oracle.jacpcg(bad.astype(np.complex128), Bm[0].T.astype(np.complex128), tol=0.0, max_iter=4)
+    assert status.item() == bd.E_BREAKDOWN and ref["instance_status"] == oracle.BREAKDOWN
+    assert iters.cpu().numpy()[0, 0] == 0 and np.all(X.cpu().numpy()[0, 0] == 0)   # zero RHS column
+    np.testing.assert_array_equal(iters.cpu().numpy()[0], ref["iters"])
+    # plain CG flag (preconditioner = identity)
+    rng = np.random.default_rng(3)
+    A = _system(rng, 1, 24, 40, xi=0.2, spread=20.0)
+    X = bd.jacpcg_solve(sess, dev(torch, A), None, tol=0.0, max_iter=6, flags=bd.PRECOND_NONE)
+    torch.cuda.synchronize()
+    ref = oracle.jacpcg(A[0].astype(np.complex128), None, tol=0.0, max_iter=6, precond="none")
+    assert rel(X.cpu().numpy()[0].T, ref["X"]) <= TOL
+
+
+# ---------------------------------------------------------------------------
+RZF_CASES = [("single", "literal", 1), ("single", "normalised", 1), ("batched", "literal", 3),
+             ("batched", "normalised", 3)]
+
+
+@pytest.mark.parametrize("name,gain,n", RZF_CASES)
+def test_rzf_fixed_iterations(torch, sess, name, gain, n):
+    w = workload(name, gain=gain)
+    H = channel_batch(w, n=n)
+    T = 8 if name == "batched" else 16
+    for xi in w.xi_values():
+        X = torch.empty((n, w.K, w.K), dtype=torch.complex64, device="cuda")
+        W, st, rc = bd.rzf_precoder(sess, dev(torch, H), xi, power=1.0, tol=0.0, max_iter=T, X_out=X, stats=True)
+        # T iterations unless the FP32 recurrence residual reached exactly zero earlier
+        assert rc == bd.OK and 1 <= st["max_iters"] <= T
+        Wn, Xn = W.cpu().numpy(), X.cpu().numpy()
+        for b in range(n):
+            Hb = H[b].T.astype(np.complex128)
+            ref = oracle.rzf(Hb, xi, tol=0.0, max_iter=T)
+            ex, ew = rel(Xn[b].T, ref["X"]), rel(Wn[b].T, ref["W"])
+            _, Wstar, _ = oracle.direct_rzf(Hb, xi)
+            print(f"{name}/{gain} xi={xi:g} b={b}: err X {ex:.2e} W {ew:.2e}; W vs FP64 direct {rel(Wn[b].T, Wstar):.2e}")
+            assert ex <= TOL and ew <= TOL
+            assert abs(np.linalg.norm(Wn[b]) ** 2 - 1.0) <= 1e-5
+
+
+def test_rzf_tolerance_mode_and_plain_path_agree(torch, sess):
+    w = workload("batched", gain="normalised")
+    H = dev(torch, channel_batch(w, n=3))
+    for xi in w.xi_values():
+        X1 = torch.empty((3, 64, 64), dtype=torch.complex64, device="cuda")
+        X2 = torch.empty_like(X1)
+        W1, s1, _ = bd.rzf_precoder(sess, H, xi, tol=1e-5, max_iter=64, X_out=X1, stats=True)
+        W2, s2, _ = bd.rzf_precoder_plain(sess, H, xi, tol=1e-5, max_iter=64, X_out=X2, stats=True)
+        torch.cuda.synchronize()
+        assert torch.equal(X1, X2) and torch.equal(W1, W2)     # same arithmetic, bitwise
+        assert s1["max_iters"] == s2["max_iters"] and s1["worst_status"] == bd.OK
+        assert s1["max_rel_residual"] <= 1e-5
+        Hn = H.cpu().numpy()
+        for b in range(3):
+            _, Wstar, _ = oracle.direct_rzf(Hn[b].T.astype(np.complex128), xi)
+            e = rel(W1.cpu().numpy()[b].T, Wstar)
+            print(f"tol 1e-5 xi={xi:g} b={b}: iters {s1['max_iters']} W vs FP64 direct {e:.2e}")
+            assert e <= 1e-3
+
+
+def test_rzf_fixed_plain_equals_batched(torch, sess):
+    rng = np.random.default_rng(11)
+    H = dev(torch, chan(rng, 4, 70, 300))
+    W1 = bd.rzf_precoder(sess, H, 0.2, tol=0.0, max_iter=5)
+    W2 = bd.rzf_precoder_plain(sess, H, 0.2, tol=0.0, max_iter=5)
+    torch.cuda.synchronize()
+    assert torch.equal(W1, W2)
+
+
+def test_rzf_deterministic(torch, sess):
+    w = workload("batched")
+    H = dev(torch, channel_batch(w, n=8))
+    a = bd.rzf_precoder(sess, H, 6.4, max_iter=8).clone()
+    b = bd.rzf_precoder(sess, H, 6.4, max_iter=8)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
+def test_rzf_closed_forms(torch, sess):
+    # K = 1: W = sqrt(P) h / ||h|| for every xi > 0
+    rng = np.random.default_rng(5)
+    h = crandn(rng, 2, 1, 50)
+    W = bd.rzf_precoder(sess, dev(torch, h), 0.7, power=2.0, tol=0.0, max_iter=3)
+    torch.cuda.synchronize()
+    for b in range(2):
+        want = np.sqrt(2.0) * h[b, 0] / np.linalg.norm(h[b, 0])
+        assert rel(W.cpu().numpy()[b, 0], want) <= TOL
+    # H = 0: A = xi I, X = I / xi after one iteration; H X = 0, so W = 0
+    Z = torch.zeros((1, 6, 40), dtype=torch.complex64, device="cuda")
+    X = torch.empty((1, 6, 6), dtype=torch.complex64, device="cuda")
+    W, st, rc = bd.rzf_precoder(sess, Z, 1.6, tol=1e-6, max_iter=16, X_out=X, stats=True)
+    assert rc == bd.OK and st["max_iters"] == 1
+    np.testing.assert_allclose(X.cpu().numpy()[0], np.eye(6) / 1.6, rtol=1e-6)
+    assert torch.count_nonzero(W).item() == 0
+
+
+def test_rzf_ragged_shapes(torch, sess):
+    rng = np.random.default_rng(21)
+    for (M, K) in [(37, 5), (129, 33), (500, 97), (77, 160)]:
+        H = chan(rng, 2, K, M, spread=3.0)
+        xi = 0.5
+        W = bd.rzf_precoder(sess, dev(torch, H), xi, tol=0.0, max_iter=6).cpu().numpy()
+        for b in range(2):
+            ref = oracle.rzf(H[b].T.astype(np.complex128), xi, tol=0.0, max_iter=6)
+            assert rel(W[b].T, ref["W"]) <= TOL, (M, K, b)
+
+
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("name,T,samples", [("batched", 8, (0, 1, 513, 1023)), ("precision", 16, (0, 255)),
+                                              ("stress", 16, (0, 63))])
+def test_full_size_sampled(torch, sess, name, T, samples):
+    """Full workload sizes in the benchmark's launch configuration; sampled
+    instances against the oracle, the power constraint on every instance."""
+    w = workload(name)
+    H = channel_batch(w)
+    xi = w.xi_values()[-1] if name == "batched" else w.xi_values()[0]
+    Hd = dev(torch, H)
+    W, st, rc = bd.rzf_precoder(sess, Hd, xi, tol=0.0, max_iter=T, stats=True)
+    assert rc == bd.OK
+    Wn = W.cpu().numpy()
+    p = np.sum(np.abs(Wn) ** 2, axis=(1, 2))
+    assert np.all(np.isfinite(p)) and np.max(np.abs(p - 1.0)) <= 1e-5
+    for b in samples:
+        ref = oracle.rzf(H[b].T.astype(np.complex128), xi, tol=0.0, max_iter=T)
+        e = rel(Wn[b].T, ref["W"])
+        print(f"{name} b={b}: W err {e:.2e}")
+        assert e <= TOL
