@@ -1,0 +1,210 @@
+"""Benchmark of the batched Jac-PCG RZF precoder on one MI355X.
+
+    python bench.py [--gpus 1] [--steps 100] [--warmup 10] [--snr-db 10] [--gain literal]
+
+One step = the whole path (regularised Gram -> persistent Jacobi-PCG with
+B = I_K -> power-normalised precoder) over one batch of 1024 subcarrier
+instances of M = 1024 antennas (8 subarrays of 128) and K = 64 users, 8 fixed
+PCG iterations, synthetic seeded channels already resident in HBM.
+
+Prints ONE JSON line: precoders/s of the batched path, the plain
+one-instance-at-a-time path on the same GPU, p50/p99 batch latency, the error
+against the FP64 direct precoder, the roofline of the dominant kernel (timed
+with HIP events on its launch stream) and the CPU oracle's throughput.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_MFMA_TFLOPS = 157.3     # MI355X dense FP32 matrix peak
+PEAK_HBM_GBS = 8000.0             # MI355X HBM3E peak
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--snr-db", type=float, default=10.0)
+    ap.add_argument("--gain", default="literal", choices=["literal", "normalised"])
+    ap.add_argument("--plain-steps", type=int, default=1)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the CPU oracle sample")
+    ap.add_argument("--no-cpu", action="store_true")
+    return ap.parse_args()
+
+
+def algorithmic(M, K, n, T, batch):
+    """Useful flops and bytes per launch of each kernel."""
+    return {
+        "gram": dict(flops=batch * 4.0 * M * K * (K + 1), bytes=batch * (8.0 * M * K + 8.0 * K * K)),
+        "solve": dict(flops=batch * T * 8.0 * K * K * n, bytes=batch * (8.0 * K * K + 8.0 * K * n)),
+        "epilogue": dict(flops=batch * 8.0 * M * K * n, bytes=batch * (8.0 * M * K + 8.0 * K * n + 8.0 * M * n)),
+    }
+
+
+def traffic_for(kernel_phase):
+    """Measured HBM bytes per launch from committed rocprofv3 counter runs,
+    valid only while the kernel sources are unchanged."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = rec.get("sources", {})
+    for f, digest in src.items():
+        p = os.path.join(ROOT, f)
+        if not os.path.exists(p) or hashlib.sha256(open(p, "rb").read()).hexdigest() != digest:
+            return None
+    v = rec.get("per_launch_bytes", {}).get(kernel_phase)
+    return float(v) if v is not None else None
+
+
+def cpu_baseline(H_host, xi, T, W_gpu, budget_s):
+    """The oracle (plain complex128 CPU implementation) on a bounded sample of
+    the same workload, plus the error of the GPU precoders of that sample
+    against the FP64 direct inverse and against the oracle at the same T."""
+    import oracle
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        threads = 1
+    n_done, t0 = 0, time.perf_counter()
+    errs_T, errs_64 = [], []
+    while n_done < H_host.shape[0] and (time.perf_counter() - t0) < budget_s:
+        Hb = H_host[n_done].T.astype(np.complex128)
+        ref = oracle.rzf(Hb, xi, tol=0.0, max_iter=T)
+        n_done += 1
+        Wg = W_gpu[n_done - 1].T
+        errs_T.append(np.linalg.norm(Wg - ref["W"]) / np.linalg.norm(ref["W"]))
+    elapsed = time.perf_counter() - t0
+    for b in range(min(8, n_done)):
+        _, Wstar, _ = oracle.direct_rzf(H_host[b].T.astype(np.complex128), xi)
+        errs_64.append(np.linalg.norm(W_gpu[b].T - Wstar) / np.linalg.norm(Wstar))
+    return dict(value=n_done / elapsed, unit="precoders/s", cores=int(threads), kind="oracle",
+                sample=f"first {n_done} of the batch's instances through oracle.rzf (complex128 Gram, "
+                       f"Jacobi-PCG T={T}, precoder), {elapsed:.1f} s"), \
+        float(np.max(errs_T)), float(np.max(errs_64)) if errs_64 else None
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {a.gpus}): instances are independent and a "
+              "multi-GPU run would shard them without communication; see DESIGN.md.", file=sys.stderr)
+        return 2
+    import torch
+    from channelgen import workload, channel_batch
+    from paper_2305_13925_amd import binding as bd
+
+    w = workload("batched", gain=a.gain)
+    M, K, T, batch = w.M, w.K, w.max_iter, w.batch
+    xi = (K / 10 ** (a.snr_db / 10.0))
+    H_host = channel_batch(w)
+    H = torch.from_numpy(H_host).to("cuda")
+    W = torch.empty_like(H)
+    sess = bd.Session(0)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        bd.rzf_precoder(sess, H, xi, power=1.0, tol=0.0, max_iter=T, W=W, stream=stream)
+
+    for _ in range(a.warmup):
+        step()
+    torch.cuda.synchronize()
+    sess.phase_times(reset=True)
+    sess.set_profiling(True)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(a.steps + 1)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    evs[0].record(stream)
+    for i in range(a.steps):
+        step()
+        evs[i + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    sess.set_profiling(False)
+    phases = sess.phase_times(reset=True)
+    lat = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(a.steps)])
+    ms_per_step = wall * 1e3 / a.steps
+    value = batch / (wall / a.steps)
+
+    # plain path: one instance at a time, one launch per iteration
+    W_plain = torch.empty_like(H)
+    bd.rzf_precoder_plain(sess, H[:8], xi, tol=0.0, max_iter=T, W=W_plain[:8], stream=stream)
+    torch.cuda.synchronize()
+    tp = time.perf_counter()
+    for _ in range(a.plain_steps):
+        bd.rzf_precoder_plain(sess, H, xi, tol=0.0, max_iter=T, W=W_plain, stream=stream)
+    torch.cuda.synchronize()
+    plain_ms = (time.perf_counter() - tp) * 1e3 / a.plain_steps
+    plain_value = batch / (plain_ms / 1e3)
+    same = bool(torch.equal(W, W_plain))
+
+    # roofline of the dominant kernel
+    alg = algorithmic(M, K, K, T, batch)
+    per_launch = {k: (phases[k][0] / phases[k][1]) if phases[k][1] else 0.0 for k in ("gram", "solve", "epilogue")}
+    dom = max(per_launch, key=per_launch.get)
+    dur_s = per_launch[dom] / 1e3
+    achieved = alg[dom]["flops"] / dur_s / 1e12
+    tr = traffic_for(dom)
+    roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_FP32_MFMA_TFLOPS, 4), "traffic": tr, "kernel": dom,
+                "avg_launch_us": round(per_launch[dom] * 1e3, 2)}
+    kernels = {}
+    for k in ("gram", "solve", "epilogue"):
+        d = per_launch[k] / 1e3
+        if d > 0:
+            kernels[k] = {"us": round(per_launch[k] * 1e3, 2),
+                          "tflops": round(alg[k]["flops"] / d / 1e12, 2),
+                          "frac_fp32_mfma": round(alg[k]["flops"] / d / 1e12 / PEAK_FP32_MFMA_TFLOPS, 4),
+                          "alg_GBs": round(alg[k]["bytes"] / d / 1e9, 1)}
+
+    cpu, err_T, err_64 = (None, None, None)
+    if not a.no_cpu:
+        cpu, err_T, err_64 = cpu_baseline(H_host, xi, T, W.cpu().numpy(), a.cpu_seconds)
+
+    out = {
+        "metric": "RZF precoders/s (M=1024,K=64) batched vs plain Jac-PCG; p99 latency; err vs FP64",
+        "value": round(value, 1),
+        "unit": "precoders/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64",
+        "data": "synthetic",
+        "config": {"workload": f"batched: {batch} x (M={M}, K={K}), 8 subarrays of 128, r=0.5, VR 3-6, "
+                               f"{a.gain} gain, SNR {a.snr_db:g} dB (xi={xi:g}), B=I_K, T={T} fixed",
+                   "batch": batch, "M": M, "K": K, "iterations": T},
+        "plain_value": round(plain_value, 1),
+        "speedup_vs_plain": round(value / plain_value, 2),
+        "plain_equals_batched_bitwise": same,
+        "p50_ms": round(float(np.percentile(lat, 50)), 4),
+        "p99_ms": round(float(np.percentile(lat, 99)), 4),
+        "err_vs_fp64": err_64,
+        "err_vs_oracle_same_T": err_T,
+        "kernels": kernels,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    sess.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
