@@ -71,10 +71,13 @@ enum {
   JACPCG_REFINE_FP64 = 0x100  /* rzf_precoder only: FP64-residual iterative refinement of X */
 };
 
-/* jacpcg_solve / rzf_precoder `flags`. */
+/* jacpcg_solve / rzf_precoder `flags` (bitwise or). */
 enum {
   JACPCG_PRECOND_JACOBI = 0,  /* C = diag(A) (eq. 21) */
-  JACPCG_PRECOND_NONE = 1     /* C = I: plain CG, the method the paper compares against */
+  JACPCG_PRECOND_NONE = 1,    /* C = I: plain CG, the method the paper compares against */
+  JACPCG_EPILOGUE_FP32 = 0x10 /* rzf_precoder*: form W = beta H X with FP32 MFMA instead of the
+                                 default split-BF16 products (three exact bf16 parts, six
+                                 products, FP32 accumulation: FP32-class accuracy) */
 };
 
 /* Kernel phases timed when profiling is on (jacpcg_session_set_profiling). */

@@ -20,4 +20,5 @@ from .binding import (  # noqa: F401
     REFINE_FP64,
     PRECOND_JACOBI,
     PRECOND_NONE,
+    EPILOGUE_FP32,
 )

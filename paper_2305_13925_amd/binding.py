@@ -42,6 +42,7 @@ GRAM_BF16X6 = 2
 REFINE_FP64 = 0x100
 PRECOND_JACOBI = 0
 PRECOND_NONE = 1
+EPILOGUE_FP32 = 0x10
 
 PHASES = ("gram", "solve", "epilogue", "gram64", "residual")
 

@@ -281,7 +281,7 @@ int rzf_precoder(jacpcg_session* s, void* stream, int batch, int M, int K, const
   JP_CHECK(std::isfinite(power) && power > 0.0, "power must be finite and > 0 (got %g)", power);
   JP_CHECK(std::isfinite(tol) && tol >= 0.0, "tol must be finite and >= 0 (got %g)", tol);
   JP_CHECK(max_iter >= 0, "max_iter must be >= 0 (got %d)", max_iter);
-  JP_CHECK(flags == JACPCG_PRECOND_JACOBI || flags == JACPCG_PRECOND_NONE, "unknown flags 0x%x", flags);
+  JP_CHECK((flags & ~(JACPCG_PRECOND_NONE | JACPCG_EPILOGUE_FP32)) == 0, "unknown flags 0x%x", flags);
   JP_CHECK(std::isfinite(refine_tol) && refine_tol >= 0.0, "refine_tol must be finite and >= 0");
   JP_CHECK(ldw >= M, "ldw must be >= M (got %lld < %d)", (long long)ldw, M);
   if (batch > 1) JP_CHECK(stride_w >= ldw * K, "stride_w must be >= ldw * K");
@@ -299,8 +299,8 @@ int rzf_precoder(jacpcg_session* s, void* stream, int batch, int M, int K, const
   JP_HIP(hipSetDevice(s->device));
   hipStream_t st = (hipStream_t)stream;
   return s->run_rzf(st, batch, M, K, (const float2*)H, ldh, stride_h, xi, power, tol, max_iter, gram_prec, refine,
-                    flags == JACPCG_PRECOND_NONE, refine_tol, (float2*)W, ldw, stride_w, (float2*)X_out,
-                    (double2*)X64_out, stats);
+                    (flags & JACPCG_PRECOND_NONE) != 0, (flags & JACPCG_EPILOGUE_FP32) == 0, refine_tol,
+                    (float2*)W, ldw, stride_w, (float2*)X_out, (double2*)X64_out, stats);
 }
 
 int rzf_precoder_plain(jacpcg_session* s, void* stream, int batch, int M, int K, const jacpcg_c64* H, int64_t ldh,
@@ -311,7 +311,7 @@ int rzf_precoder_plain(jacpcg_session* s, void* stream, int batch, int M, int K,
   JP_CHECK(std::isfinite(power) && power > 0.0, "power must be finite and > 0 (got %g)", power);
   JP_CHECK(std::isfinite(tol) && tol >= 0.0, "tol must be finite and >= 0 (got %g)", tol);
   JP_CHECK(max_iter >= 0, "max_iter must be >= 0 (got %d)", max_iter);
-  JP_CHECK(flags == JACPCG_PRECOND_JACOBI || flags == JACPCG_PRECOND_NONE, "unknown flags 0x%x", flags);
+  JP_CHECK((flags & ~(JACPCG_PRECOND_NONE | JACPCG_EPILOGUE_FP32)) == 0, "unknown flags 0x%x", flags);
   JP_CHECK(ldw >= M, "ldw must be >= M (got %lld < %d)", (long long)ldw, M);
   if (batch > 1) JP_CHECK(stride_w >= ldw * K, "stride_w must be >= ldw * K");
   if (batch > 0) JP_CHECK(W != nullptr, "W is NULL");
@@ -323,7 +323,8 @@ int rzf_precoder_plain(jacpcg_session* s, void* stream, int batch, int M, int K,
   }
   JP_HIP(hipSetDevice(s->device));
   return s->run_rzf_plain((hipStream_t)stream, batch, M, K, (const float2*)H, ldh, stride_h, xi, power, tol,
-                          max_iter, flags == JACPCG_PRECOND_NONE, (float2*)W, ldw, stride_w, (float2*)X_out, stats);
+                          max_iter, (flags & JACPCG_PRECOND_NONE) != 0, (flags & JACPCG_EPILOGUE_FP32) == 0,
+                          (float2*)W, ldw, stride_w, (float2*)X_out, stats);
 }
 
 }  // extern "C"

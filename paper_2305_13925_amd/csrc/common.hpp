@@ -81,6 +81,7 @@ struct PrecoderLaunch {
   const float* fpart; int ncb;              // per instance: ncb partial ||H X||^2 terms
   float power;
   float* beta_out;                          // batch (nullable)
+  int split;                                // 0: FP32 MFMA; 3: split-BF16 (3 parts, six products)
 };
 
 struct Gram64Launch {

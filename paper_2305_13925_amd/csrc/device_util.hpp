@@ -26,3 +26,74 @@ __device__ __forceinline__ floatx16 zero16() {
 }
 
 }  // namespace jacpcg
+
+namespace jacpcg {
+
+// ---------------------------------------------------------------------------
+// Split-BF16 products. An FP32 value x is written as a sum of NS bfloat16
+// parts, each the round-to-nearest bfloat16 of what the previous parts left:
+// NS = 2 gives x ~ hi + lo (16 significant bits), NS = 3 gives x = hi + mid + lo
+// exactly (8 + 8 + 8 bits, |mid| <= 2^-8 |x|, |lo| <= 2^-16 |x|). Products of
+// parts are exact in the MFMA's FP32 accumulation. With NS = 3, keeping hi*hi,
+// hi*mid, mid*hi, hi*lo, lo*hi and mid*mid drops mid*lo, lo*mid and lo*lo, at
+// most 2^-23 of the product together: the size of one FP32 rounding. With
+// NS = 2 (hi*hi + hi*lo + lo*hi) the dropped part is up to ~2^-16.
+// ---------------------------------------------------------------------------
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float floatv2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint32_t pack_bf16x2(float a, float b) {
+  const floatv2 v = {a, b};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));
+}
+__device__ __forceinline__ float bf16_lo(uint32_t p) { return __uint_as_float(p << 16); }
+__device__ __forceinline__ float bf16_hi(uint32_t p) { return __uint_as_float(p & 0xffff0000u); }
+
+// Split 8 floats (4 packed pairs: x[0..1], x[2..3], ...) into NS bf16 parts of
+// 4 packed pairs each.
+template <int NS>
+__device__ __forceinline__ void split8(const float (&x)[8], u32x4 (&parts)[NS]) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    float a = x[2 * q], b = x[2 * q + 1];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const uint32_t p = pack_bf16x2(a, b);
+      parts[s][q] = p;
+      if (s + 1 < NS) {
+        a -= bf16_lo(p);
+        b -= bf16_hi(p);
+      }
+    }
+  }
+}
+
+// Negate every bf16 of a packed pair.
+__device__ __forceinline__ uint32_t neg_bf16x2(uint32_t p) { return p ^ 0x80008000u; }
+// (re, im) packed pair -> (im, -re)
+__device__ __forceinline__ uint32_t rot_neg_hi(uint32_t p) { return ((p >> 16) | (p << 16)) ^ 0x80000000u; }
+// (re, -im) packed pair -> (im, re)
+__device__ __forceinline__ uint32_t rot_neg_lo(uint32_t p) { return ((p >> 16) | (p << 16)) ^ 0x00008000u; }
+
+__device__ __forceinline__ floatx16 mfma_bf16(u32x4 a, u32x4 b, floatx16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c, 0,
+                                                 0, 0);
+}
+
+// acc += the significant part products of a*b, smallest first. One MFMA adds 16
+// products into the FP32 accumulator, so a split-BF16 product chain rounds less
+// often than the FP32 MFMA chain it replaces (which adds 2 products per step).
+template <int NS>
+__device__ __forceinline__ void split_mma(const u32x4 (&a)[NS], const u32x4 (&b)[NS], floatx16& acc) {
+  if constexpr (NS >= 3) {
+    acc = mfma_bf16(a[1], b[1], acc);
+    acc = mfma_bf16(a[0], b[2], acc);
+    acc = mfma_bf16(a[2], b[0], acc);
+  }
+  acc = mfma_bf16(a[0], b[1], acc);
+  acc = mfma_bf16(a[1], b[0], acc);
+  acc = mfma_bf16(a[0], b[0], acc);
+}
+
+}  // namespace jacpcg

@@ -49,6 +49,98 @@ __device__ __forceinline__ void load8(const float2* __restrict__ row, int m, int
 
 constexpr int kGramMaxWaves = 8;
 
+// Panels: tile row ti of the upper triangle cut into groups of up to two tiles.
+__host__ __device__ inline int panels_per_instance(int nt) {
+  int n = 0;
+  for (int ti = 0; ti < nt; ++ti) n += (nt - ti + 1) / 2;
+  return n;
+}
+
+__device__ __forceinline__ void panel_tiles(int p, int nt, int& ti, int& tj0, int& ntj) {
+  for (ti = 0; ti < nt; ++ti) {
+    const int np = (nt - ti + 1) / 2;
+    if (p < np) break;
+    p -= np;
+  }
+  tj0 = ti + 2 * p;
+  ntj = min(2, nt - tj0);
+}
+
+// 4 consecutive complex entries row[m .. m+3] as 8 floats (re, im, ...), zero
+// past `mend` or for a padding row.
+template <bool VEC>
+__device__ __forceinline__ void load4c(const float2* __restrict__ row, int m, int mend, bool valid, float (&v)[8]) {
+  if (VEC && valid && m + 4 <= mend) {
+    const float4* p = reinterpret_cast<const float4*>(row + m);
+    const float4 a = p[0], c = p[1];
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+    v[4] = c.x; v[5] = c.y; v[6] = c.z; v[7] = c.w;
+  } else {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const float2 t = (valid && m + e < mend) ? row[m + e] : make_float2(0.f, 0.f);
+      v[2 * e] = t.x;
+      v[2 * e + 1] = t.y;
+    }
+  }
+}
+
+// Sum the waves' partial tiles (fixed wave order) and write tile (ti, tj) of A
+// plus its conjugate mirror; the diagonal tile is mirrored inside itself and
+// gets xi added to an exactly real diagonal. `red` holds nw * 2 * 16 * 64
+// floats of LDS.
+__device__ void reduce_and_write_tile(const GramLaunch& g, float* red_raw, const floatx16& accR,
+                                      const floatx16& accI, int b, int ti, int tj, int wave, int nw, int lane) {
+  float(*red)[2][16][64] = reinterpret_cast<float(*)[2][16][64]>(red_raw);
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    red[wave][0][r][lane] = accR[r];
+    red[wave][1][r][lane] = accI[r];
+  }
+  __syncthreads();
+  // Tile element (i, j) sits in lane j + 32*((i>>2)&1), register 4*(i>>3) + (i&3).
+  auto tile = [&](int i, int j, float& re, float& im) {
+    const int l = j + 32 * ((i >> 2) & 1), r = 4 * (i >> 3) + (i & 3);
+    re = 0.f;
+    im = 0.f;
+    for (int w = 0; w < nw; ++w) {
+      re += red[w][0][r][l];
+      im += red[w][1][r][l];
+    }
+  };
+  const bool same = (ti == tj);
+  float2* Ab = g.A + (int64_t)b * g.stride_a;
+  for (int e = threadIdx.x; e < 1024; e += blockDim.x) {
+    const int i = e >> 5, j = e & 31;
+    const int gi = ti * 32 + i, gj = tj * 32 + j;
+    if (gi < g.K && gj < g.K) {
+      float re, im;
+      if (!same || i < j) {
+        tile(i, j, re, im);
+      } else if (i > j) {
+        tile(j, i, re, im);  // Hermitian mirror inside a diagonal tile
+        im = -im;
+      } else {
+        tile(i, i, re, im);
+        if (g.gdiag) g.gdiag[(int64_t)b * g.K + gi] = re;
+        re += g.xi;
+        im = 0.f;
+        if (g.diag) g.diag[(int64_t)b * g.K + gi] = re;
+      }
+      Ab[(int64_t)gi * g.lda + gj] = make_float2(re, im);
+    }
+    if (!same) {
+      // Mirror tile (tj, ti): row tj*32 + i, column ti*32 + j holds conj(T[j][i]).
+      const int mi = tj * 32 + i, mj = ti * 32 + j;
+      if (mi < g.K && mj < g.K) {
+        float re, im;
+        tile(j, i, re, im);
+        Ab[(int64_t)mi * g.lda + mj] = make_float2(re, -im);
+      }
+    }
+  }
+}
+
 template <bool VEC>
 __global__ __launch_bounds__(512) void gram_f32_kernel(GramLaunch g) {
   const int nt = (g.K + 31) >> 5;
@@ -91,76 +183,270 @@ __global__ __launch_bounds__(512) void gram_f32_kernel(GramLaunch g) {
     }
   }
 
-  // Fixed-order cross-wave sum through LDS.
-  // red[w][0|1][r][lane]: nw * 2 * 16 * 64 floats of dynamic LDS.
   extern __shared__ float red_dyn[];
-  float(*red)[2][16][64] = reinterpret_cast<float(*)[2][16][64]>(red_dyn);
-#pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    red[wave][0][r][lane] = accR[r];
-    red[wave][1][r][lane] = accI[r];
-  }
-  __syncthreads();
+  reduce_and_write_tile(g, red_dyn, accR, accI, b, ti, tj, wave, nw, lane);
+}
 
-  // Tile element (i, j) sits in lane j + 32*((i>>2)&1), register 4*(i>>3) + (i&3).
-  auto tile = [&](int i, int j, float& re, float& im) {
-    const int l = j + 32 * ((i >> 2) & 1), r = 4 * (i >> 3) + (i & 3);
-    re = 0.f;
-    im = 0.f;
-    for (int w = 0; w < nw; ++w) {
-      re += red[w][0][r][l];
-      im += red[w][1][r][l];
+// Split-BF16 Gram: one workgroup per (instance, panel of up to two tiles of one
+// tile row), so the split of the row block's users is shared by both tiles.
+// Real-plane formulation on v_mfma_f32_32x32x16_bf16: the 16 k slots are 16
+// antennas (lane half c holds antennas m+8c .. m+8c+7) of one component, and
+//   Re A_ij = sum_m Re h_im Re h_jm + Im h_im Im h_jm
+//   Im A_ij = sum_m Re h_im Im h_jm + (-Im h_im) Re h_jm
+// so each tile takes four split products per 16 antennas and the only extra
+// work is one negation of the row block's imaginary plane, shared by the panel.
+template <int NS, bool VEC>
+__global__ __launch_bounds__(256) void gram_bf16_kernel(GramLaunch g) {
+  const int nt = (g.K + 31) >> 5;
+  const int npanel = panels_per_instance(nt);
+  const int L = xcd_remap(blockIdx.x, gridDim.x);
+  const int b = L / npanel;
+  int ti, tj0, ntj;
+  panel_tiles(L - b * npanel, nt, ti, tj0, ntj);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
+  const int half = lane >> 5, li = lane & 31;
+  const float2* Hb = g.H + (int64_t)b * g.stride_h;
+  const int ui = ti * 32 + li;
+  const bool vi = ui < g.K;
+  const float2* hi = Hb + (int64_t)(vi ? ui : 0) * g.ldh;
+  // Tile t of the panel is (ti, tj0 + t). The diagonal tile reuses the row
+  // block; every other tile has its own column block of users, loaded and split.
+  const bool diag0 = (tj0 == ti);
+  const int nx = ntj - (diag0 ? 1 : 0);  // 0, 1 or 2 column blocks to load
+  const int xoff = diag0 ? 1 : 0;        // tile index of column block q is q + xoff
+  bool vx[2];
+  const float2* hx[2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int ux = (tj0 + q + xoff) * 32 + li;
+    vx[q] = (q < nx) && ux < g.K;
+    hx[q] = Hb + (int64_t)(vx[q] ? ux : 0) * g.ldh;
+  }
+
+  const int chunk = ((g.M + nw * 16 - 1) / (nw * 16)) * 16;
+  const int m0 = wave * chunk;
+  const int m1 = min(g.M, m0 + chunk);
+
+  floatx16 accR[2], accI[2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    accR[t] = zero16();
+    accI[t] = zero16();
+  }
+  auto load = [&](const float2* row, bool valid, int m, float (&re)[8], float (&im)[8]) {
+    const int mm = m + 8 * half;
+    if (VEC && valid && mm + 8 <= m1) {
+      const float4* p = reinterpret_cast<const float4*>(row + mm);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float4 t = p[q];
+        re[2 * q] = t.x;
+        im[2 * q] = t.y;
+        re[2 * q + 1] = t.z;
+        im[2 * q + 1] = t.w;
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const float2 t = (valid && mm + e < m1) ? row[mm + e] : make_float2(0.f, 0.f);
+        re[e] = t.x;
+        im[e] = t.y;
+      }
     }
   };
-
-  float2* Ab = g.A + (int64_t)b * g.stride_a;
-  for (int e = threadIdx.x; e < 1024; e += blockDim.x) {
-    const int i = e >> 5, j = e & 31;
-    const int gi = ti * 32 + i, gj = tj * 32 + j;
-    if (gi < g.K && gj < g.K) {
-      float re, im;
-      if (!same || i < j) {
-        tile(i, j, re, im);
-      } else if (i > j) {
-        tile(j, i, re, im);  // Hermitian mirror inside a diagonal tile
-        im = -im;
-      } else {
-        tile(i, i, re, im);
-        if (g.gdiag) g.gdiag[(int64_t)b * g.K + gi] = re;
-        re += g.xi;
-        im = 0.f;
-        if (g.diag) g.diag[(int64_t)b * g.K + gi] = re;
-      }
-      Ab[(int64_t)gi * g.lda + gj] = make_float2(re, im);
+  for (int m = m0; m < m1; m += 16) {
+    float ri[8], ii[8], rx[2][8], ix[2][8];
+    load(hi, vi, m, ri, ii);
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+      if (q < nx) load(hx[q], vx[q], m, rx[q], ix[q]);
+    u32x4 Ar[NS], Ai[NS], An[NS];
+    split8<NS>(ri, Ar);
+    split8<NS>(ii, Ai);
+#pragma unroll
+    for (int q = 0; q < NS; ++q)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) An[q][e] = neg_bf16x2(Ai[q][e]);
+    if (diag0) {
+      split_mma<NS>(Ar, Ar, accR[0]);
+      split_mma<NS>(Ai, Ai, accR[0]);
+      split_mma<NS>(Ar, Ai, accI[0]);
+      split_mma<NS>(An, Ar, accI[0]);
     }
-    if (!same) {
-      // Mirror tile (tj, ti): row tj*32 + i, column ti*32 + j holds conj(T[j][i]).
-      const int mi = tj * 32 + i, mj = ti * 32 + j;
-      if (mi < g.K && mj < g.K) {
-        float re, im;
-        tile(j, i, re, im);
-        Ab[(int64_t)mi * g.lda + mj] = make_float2(re, -im);
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      if (q >= nx) break;
+      u32x4 Xr[NS], Xi[NS];
+      split8<NS>(rx[q], Xr);
+      split8<NS>(ix[q], Xi);
+      floatx16& aR = accR[q + xoff];
+      floatx16& aI = accI[q + xoff];
+      split_mma<NS>(Ar, Xr, aR);
+      split_mma<NS>(Ai, Xi, aR);
+      split_mma<NS>(Ar, Xi, aI);
+      split_mma<NS>(An, Xr, aI);
+    }
+  }
+
+  extern __shared__ float red_dyn[];
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    if (t >= ntj) break;
+    if (t > 0) __syncthreads();  // previous tile's write-out has read the buffer
+    reduce_and_write_tile(g, red_dyn, accR[t], accI[t], b, ti, tj0 + t, wave, nw, lane);
+  }
+}
+
+
+// Split-BF16 Gram for K <= 64: one workgroup per instance; each wave takes a
+// contiguous quarter of the antennas, splits each of the (at most two) user
+// blocks once per 16 antennas and forms all upper tiles (0,0), (0,1), (1,1)
+// from those splits, so the split work per MFMA is a third of the panel
+// kernel's. The next step's channel values are loaded before the products.
+template <int NS, int NT>
+__global__ __launch_bounds__(256) void gram_bf16_small_kernel(GramLaunch g) {
+  constexpr int NTILE = NT * (NT + 1) / 2;
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
+  const int half = lane >> 5, li = lane & 31;
+  const float2* Hb = g.H + (int64_t)b * g.stride_h;
+  bool vu[NT];
+  const float2* row[NT];
+#pragma unroll
+  for (int q = 0; q < NT; ++q) {
+    const int u = q * 32 + li;
+    vu[q] = u < g.K;
+    row[q] = Hb + (int64_t)(vu[q] ? u : 0) * g.ldh;
+  }
+  const int chunk = ((g.M + nw * 16 - 1) / (nw * 16)) * 16;
+  const int m0 = wave * chunk;
+  const int m1 = min(g.M, m0 + chunk);
+  const bool vec = ((uintptr_t)g.H % 16 == 0) && (g.ldh % 2 == 0) && (g.stride_h % 2 == 0);
+
+  floatx16 accR[NTILE], accI[NTILE];
+#pragma unroll
+  for (int t = 0; t < NTILE; ++t) {
+    accR[t] = zero16();
+    accI[t] = zero16();
+  }
+  auto load = [&](int q, int m, float (&re)[8], float (&im)[8]) {
+    const int mm = m + 8 * half;
+    if (vec && vu[q] && mm + 8 <= m1) {
+      const float4* p = reinterpret_cast<const float4*>(row[q] + mm);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const float4 t = p[c];
+        re[2 * c] = t.x;
+        im[2 * c] = t.y;
+        re[2 * c + 1] = t.z;
+        im[2 * c + 1] = t.w;
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const float2 t = (vu[q] && mm + e < m1) ? row[q][mm + e] : make_float2(0.f, 0.f);
+        re[e] = t.x;
+        im[e] = t.y;
+      }
+    }
+  };
+  float re[NT][8], im[NT][8];
+  if (m0 < m1) {
+#pragma unroll
+    for (int q = 0; q < NT; ++q) load(q, m0, re[q], im[q]);
+  }
+  for (int m = m0; m < m1; m += 16) {
+    u32x4 Pr[NT][NS], Pi[NT][NS];
+#pragma unroll
+    for (int q = 0; q < NT; ++q) {
+      split8<NS>(re[q], Pr[q]);
+      split8<NS>(im[q], Pi[q]);
+    }
+    if (m + 16 < m1) {
+#pragma unroll
+      for (int q = 0; q < NT; ++q) load(q, m + 16, re[q], im[q]);
+    }
+    int t = 0;
+#pragma unroll
+    for (int a = 0; a < NT; ++a) {
+      u32x4 An[NS];
+#pragma unroll
+      for (int s2 = 0; s2 < NS; ++s2)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) An[s2][e] = neg_bf16x2(Pi[a][s2][e]);
+#pragma unroll
+      for (int c = a; c < NT; ++c, ++t) {
+        split_mma<NS>(Pr[a], Pr[c], accR[t]);
+        split_mma<NS>(Pi[a], Pi[c], accR[t]);
+        split_mma<NS>(Pr[a], Pi[c], accI[t]);
+        split_mma<NS>(An, Pr[c], accI[t]);
       }
     }
   }
+
+  extern __shared__ float red_dyn[];
+  int t = 0;
+#pragma unroll
+  for (int a = 0; a < NT; ++a)
+#pragma unroll
+    for (int c = a; c < NT; ++c, ++t) {
+      if (t > 0) __syncthreads();  // previous tile's write-out has read the buffer
+      reduce_and_write_tile(g, red_dyn, accR[t], accI[t], b, a, c, wave, nw, lane);
+    }
 }
 
 }  // namespace
 
 hipError_t launch_gram(const GramLaunch& g, hipStream_t s) {
   if (g.batch == 0) return hipSuccess;
-  if (g.precision != 0) return hipErrorNotSupported;
+  if (g.precision < 0 || g.precision > 2) return hipErrorNotSupported;
   const int nt = (g.K + 31) / 32;
-  const int ntiles = nt * (nt + 1) / 2;
   int waves = g.m_split > 0 ? g.m_split : 4;
   if (waves > kGramMaxWaves) waves = kGramMaxWaves;
-  const dim3 grid((unsigned)(ntiles * g.batch)), block(64 * waves);
+  const dim3 block(64 * waves);
   const bool vec = ((uintptr_t)g.H % 16 == 0) && (g.ldh % 2 == 0) && (g.stride_h % 2 == 0);
   const size_t lds = (size_t)waves * 2 * 16 * 64 * sizeof(float);
-  if (vec)
-    hipLaunchKernelGGL(gram_f32_kernel<true>, grid, block, lds, s, g);
-  else
-    hipLaunchKernelGGL(gram_f32_kernel<false>, grid, block, lds, s, g);
+  if (g.precision == 0) {
+    const dim3 grid((unsigned)(nt * (nt + 1) / 2 * g.batch));
+    if (vec)
+      hipLaunchKernelGGL(gram_f32_kernel<true>, grid, block, lds, s, g);
+    else
+      hipLaunchKernelGGL(gram_f32_kernel<false>, grid, block, lds, s, g);
+  } else {
+    // The split kernel is compiled for at most 256 threads (register budget).
+    const int wb = waves > 4 ? 4 : waves;
+    const dim3 block(64 * wb);
+    const size_t lds = (size_t)wb * 2 * 16 * 64 * sizeof(float);
+    if (nt <= 2) {
+      const dim3 grid1((unsigned)g.batch);
+      if (g.precision == 1) {
+        if (nt == 1)
+          hipLaunchKernelGGL((gram_bf16_small_kernel<2, 1>), grid1, block, lds, s, g);
+        else
+          hipLaunchKernelGGL((gram_bf16_small_kernel<2, 2>), grid1, block, lds, s, g);
+      } else {
+        if (nt == 1)
+          hipLaunchKernelGGL((gram_bf16_small_kernel<3, 1>), grid1, block, lds, s, g);
+        else
+          hipLaunchKernelGGL((gram_bf16_small_kernel<3, 2>), grid1, block, lds, s, g);
+      }
+      return hipGetLastError();
+    }
+    const dim3 grid((unsigned)(panels_per_instance(nt) * g.batch));
+    if (g.precision == 1) {
+      if (vec)
+        hipLaunchKernelGGL((gram_bf16_kernel<2, true>), grid, block, lds, s, g);
+      else
+        hipLaunchKernelGGL((gram_bf16_kernel<2, false>), grid, block, lds, s, g);
+    } else {
+      if (vec)
+        hipLaunchKernelGGL((gram_bf16_kernel<3, true>), grid, block, lds, s, g);
+      else
+        hipLaunchKernelGGL((gram_bf16_kernel<3, false>), grid, block, lds, s, g);
+    }
+  }
   return hipGetLastError();
 }
 

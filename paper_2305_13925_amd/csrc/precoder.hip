@@ -132,10 +132,171 @@ hipError_t launch_kt(const PrecoderLaunch& e, hipStream_t s) {
   return hipGetLastError();
 }
 
+
+// Split-BF16 precoder (FP32-class accuracy with NS = 3). It computes the
+// transpose W^T = X^T H^T so that the MFMA result puts consecutive antennas in
+// consecutive lanes and every W store is a coalesced 256-byte row segment.
+// Real-plane formulation on v_mfma_f32_32x32x16_bf16: the 16 k slots are 16
+// users of one component (lane half c holds users k0+8c .. k0+8c+7):
+//   Re W[m,j] = sum_k Re X[k,j] Re H[m,k] + Im X[k,j] (-Im H[m,k])
+//   Im W[m,j] = sum_k Re X[k,j] Im H[m,k] + Im X[k,j]   Re H[m,k]
+// beta_pow X is split into bf16 parts once per workgroup (Re and Im planes in
+// LDS); H is split on the fly and its negated Im plane is shared by all column
+// tiles, so no other operand shuffling is needed.
+template <int NS, int KT, int NJ, int MT, bool FULL>
+__global__ __launch_bounds__(256) void precoder_bf16_kernel(PrecoderLaunch e) {
+  constexpr int KP = KT * 32;
+  constexpr int K8 = KP / 8;  // groups of 8 users (one lane half of one step)
+  constexpr int NC = 32 * NJ;
+  constexpr int MB = 128 * MT;  // antennas per workgroup: MT tiles of 32 per wave
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int jl = lane & 31, half = lane >> 5;
+  const int nmb = (e.M + MB - 1) / MB;
+  const int ncw = (e.nrhs + NC - 1) / NC;
+  const int per = nmb * ncw;
+  const int L = xcd_remap(blockIdx.x, gridDim.x);
+  const int b = L / per;
+  const int rem = L - b * per;
+  const int mb = rem / ncw, cw = rem - mb * ncw;
+  const int K = e.K;
+
+  extern __shared__ u32x4 xs_dyn[];  // [2 planes][NS][K8][NC]
+  auto XS = [&](int plane, int s, int k8, int j) -> u32x4& {
+    return xs_dyn[(((size_t)plane * NS + s) * K8 + k8) * NC + j];
+  };
+
+  float fs = 0.f;
+  for (int c = 0; c < e.ncb; ++c) fs += e.fpart[(int64_t)b * e.ncb + c];
+  const float beta = fs > 0.f ? sqrtf(e.power / fs) : 0.f;
+  if (e.beta_out && mb == 0 && cw == 0 && threadIdx.x == 0) e.beta_out[b] = beta;
+
+  const float2* Xb = e.X + (int64_t)b * e.stride_x;
+  for (int idx = threadIdx.x; idx < K8 * NC; idx += 256) {
+    const int jj = idx % NC, k8 = idx / NC;
+    const int j = cw * NC + jj;
+    float re[8], im[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int k = 8 * k8 + u;
+      float2 x = make_float2(0.f, 0.f);
+      if (k < K && j < e.nrhs) x = Xb[(int64_t)j * e.ldx + k];
+      re[u] = beta * x.x;
+      im[u] = beta * x.y;
+    }
+    u32x4 pr[NS], pi[NS];
+    split8<NS>(re, pr);
+    split8<NS>(im, pi);
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+      XS(0, q, k8, jj) = pr[q];
+      XS(1, q, k8, jj) = pi[q];
+    }
+  }
+  __syncthreads();
+
+#pragma unroll 1
+  for (int mt = 0; mt < MT; ++mt) {
+    const int m = mb * MB + (mt * 4 + w) * 32 + jl;
+    const bool mvalid = FULL || m < e.M;
+    const float2* hcol = e.H + (int64_t)b * e.stride_h + (mvalid ? m : 0);
+
+    floatx16 wr[NJ], wi[NJ];
+#pragma unroll
+    for (int t = 0; t < NJ; ++t) {
+      wr[t] = zero16();
+      wi[t] = zero16();
+    }
+    float hr[8], hi[8];
+    auto load_h = [&](int k8) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int k = 8 * k8 + u;
+        const float2 h = (FULL || (mvalid && k < K)) ? hcol[(int64_t)k * e.ldh] : make_float2(0.f, 0.f);
+        hr[u] = h.x;
+        hi[u] = h.y;
+      }
+    };
+    load_h(half);
+    for (int step = 0; step < K8 / 2; ++step) {
+      const int k8 = 2 * step + half;
+      u32x4 Hr[NS], Hi[NS], Hn[NS];
+      split8<NS>(hr, Hr);
+      split8<NS>(hi, Hi);
+      if (step + 1 < K8 / 2) load_h(k8 + 2);  // next users in flight during the products
+#pragma unroll
+      for (int q = 0; q < NS; ++q)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) Hn[q][c] = neg_bf16x2(Hi[q][c]);
+#pragma unroll
+      for (int t = 0; t < NJ; ++t) {
+        u32x4 Xr[NS], Xi[NS];
+#pragma unroll
+        for (int q = 0; q < NS; ++q) {
+          Xr[q] = XS(0, q, k8, t * 32 + jl);
+          Xi[q] = XS(1, q, k8, t * 32 + jl);
+        }
+        split_mma<NS>(Xr, Hr, wr[t]);
+        split_mma<NS>(Xi, Hn, wr[t]);
+        split_mma<NS>(Xr, Hi, wi[t]);
+        split_mma<NS>(Xi, Hr, wi[t]);
+      }
+    }
+
+    if (mvalid) {
+      float2* Wb = e.W + (int64_t)b * e.stride_w + m;
+#pragma unroll
+      for (int t = 0; t < NJ; ++t) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int j = cw * NC + t * 32 + d32_row(r, half);
+          if (FULL || j < e.nrhs) Wb[(int64_t)j * e.ldw] = make_float2(wr[t][r], wi[t][r]);
+        }
+      }
+    }
+  }
+}
+
+template <int NS, int KT, int NJ>
+hipError_t launch_bf16_nj(const PrecoderLaunch& e, hipStream_t s) {
+  constexpr int K8 = KT * 4;
+  constexpr int MT = 1;  // antenna tiles per wave (2 doubles the register footprint at K = 64)
+  const int nmb = (e.M + 128 * MT - 1) / (128 * MT);
+  const size_t lds = (size_t)2 * NS * K8 * 32 * NJ * 16;
+  // FULL: every user, antenna and column of every tile is in range (no masks).
+  const bool full = (e.K == KT * 32) && (e.M % (128 * MT) == 0) && (e.nrhs % (32 * NJ) == 0);
+  const int grid = e.batch * nmb * ((e.nrhs + 32 * NJ - 1) / (32 * NJ));
+  auto kf = precoder_bf16_kernel<NS, KT, NJ, MT, true>;
+  auto km = precoder_bf16_kernel<NS, KT, NJ, MT, false>;
+  auto k = full ? kf : km;
+  if (lds > 65536) (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL(k, dim3(grid), dim3(256), lds, s, e);
+  return hipGetLastError();
+}
+
+template <int NS, int KT>
+hipError_t launch_bf16_kt(const PrecoderLaunch& e, hipStream_t s) {
+  if constexpr (KT <= 2) {
+    if (e.nrhs > 32) return launch_bf16_nj<NS, KT, 2>(e, s);
+  }
+  return launch_bf16_nj<NS, KT, 1>(e, s);
+}
 }  // namespace
 
 hipError_t launch_precoder(const PrecoderLaunch& e, hipStream_t s) {
   if (e.batch == 0) return hipSuccess;
+  if (e.split == 3) {
+    switch ((e.K + 31) / 32) {
+      case 1: return launch_bf16_kt<3, 1>(e, s);
+      case 2: return launch_bf16_kt<3, 2>(e, s);
+      case 3: return launch_bf16_kt<3, 3>(e, s);
+      case 4: return launch_bf16_kt<3, 4>(e, s);
+      case 5: return launch_bf16_kt<3, 5>(e, s);
+      case 6: return launch_bf16_kt<3, 6>(e, s);
+      case 7: return launch_bf16_kt<3, 7>(e, s);
+      case 8: return launch_bf16_kt<3, 8>(e, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
   switch ((e.K + 31) / 32) {
     case 1: return launch_kt<1>(e, s);
     case 2: return launch_kt<2>(e, s);

@@ -104,7 +104,8 @@ void jacpcg_session::shutdown() {
 // ---------------------------------------------------------------------------
 int jacpcg_session::run_rzf(hipStream_t st, int batch, int M, int K, const float2* H, int64_t ldh, int64_t stride_h,
                             double xi, double power, double tol, int max_iter, int gram_prec, bool refine,
-                            bool precond_none, double refine_tol, float2* W, int64_t ldw, int64_t stride_w,
+                            bool precond_none, bool split_epilogue, double refine_tol, float2* W, int64_t ldw,
+                            int64_t stride_w,
                             float2* X_out, double2* X64_out, jacpcg_stats* stats) {
   (void)refine_tol;
   if (refine) return set_error(JACPCG_E_UNSUPPORTED, "FP64 refinement not available in this build");
@@ -194,6 +195,7 @@ int jacpcg_session::run_rzf(hipStream_t st, int batch, int M, int K, const float
   E.ncb = ncb;
   E.power = (float)power;
   E.beta_out = beta;
+  E.split = split_epilogue ? 3 : 0;
   e = timed(st, JACPCG_PHASE_EPILOGUE, [&] { return launch_precoder(E, st); });
   if (e != hipSuccess) return hip_error(this, e, "precoder launch");
 
@@ -224,7 +226,8 @@ int jacpcg_session::run_rzf(hipStream_t st, int batch, int M, int K, const float
 // ---------------------------------------------------------------------------
 int jacpcg_session::run_rzf_plain(hipStream_t st, int batch, int M, int K, const float2* H, int64_t ldh,
                                   int64_t stride_h, double xi, double power, double tol, int max_iter,
-                                  bool precond_none, float2* W, int64_t ldw, int64_t stride_w, float2* X_out,
+                                  bool precond_none, bool split_epilogue, float2* W, int64_t ldw, int64_t stride_w,
+                                  float2* X_out,
                                   jacpcg_stats* stats) {
   const int ncb = (K + 31) / 32;
   const size_t KK = (size_t)K * K;
@@ -329,6 +332,7 @@ int jacpcg_session::run_rzf_plain(hipStream_t st, int batch, int M, int K, const
     E.ncb = ncb;
     E.power = (float)power;
     E.beta_out = beta + b;
+    E.split = split_epilogue ? 3 : 0;
     e = timed(st, JACPCG_PHASE_EPILOGUE, [&] { return launch_precoder(E, st); });
     if (e != hipSuccess) return hip_error(this, e, "precoder launch");
   }

@@ -80,9 +80,10 @@ struct jacpcg_session {
 
   int run_rzf(hipStream_t st, int batch, int M, int K, const float2* H, int64_t ldh, int64_t stride_h, double xi,
               double power, double tol, int max_iter, int gram_prec, bool refine, bool precond_none,
-              double refine_tol, float2* W, int64_t ldw, int64_t stride_w, float2* X_out, double2* X64_out,
+              bool split_epilogue, double refine_tol, float2* W, int64_t ldw, int64_t stride_w, float2* X_out, double2* X64_out,
               jacpcg_stats* stats);
   int run_rzf_plain(hipStream_t st, int batch, int M, int K, const float2* H, int64_t ldh, int64_t stride_h,
-                    double xi, double power, double tol, int max_iter, bool precond_none, float2* W, int64_t ldw,
+                    double xi, double power, double tol, int max_iter, bool precond_none, bool split_epilogue,
+                    float2* W, int64_t ldw,
                     int64_t stride_w, float2* X_out, jacpcg_stats* stats);
 };

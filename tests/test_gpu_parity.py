@@ -74,6 +74,29 @@ def test_gram_parity(torch, sess, M, K, batch):
         np.testing.assert_array_equal(d[b], A[b].diagonal().real.astype(np.float32))
 
 
+@pytest.mark.parametrize("prec", [bd.GRAM_BF16X6, bd.GRAM_BF16X3])
+@pytest.mark.parametrize("M,K,batch", [(1024, 64, 2), (333, 70, 2), (4100, 96, 1), (64, 256, 1), (7, 5, 3),
+                                       (1000, 130, 1)])
+def test_gram_split_bf16_parity(torch, sess, prec, M, K, batch):
+    # Split-BF16 Gram: three exact parts / six products is FP32-class; hi+lo
+    # with three products carries ~2^-16 relative product error.
+    rng = np.random.default_rng(M + 31 * K)
+    H = chan(rng, batch, K, M)
+    xi = 0.37
+    diag = torch.empty((batch, K), dtype=torch.float32, device="cuda")
+    A = bd.jacpcg_gram(sess, dev(torch, H), xi, precision=prec, diag=diag)
+    torch.cuda.synchronize()
+    A = A.cpu().numpy().astype(np.complex128)
+    for b in range(batch):
+        ref = oracle.gram(H[b].T, xi)
+        e = rel(A[b], ref)
+        print(f"gram precision {prec} M={M} K={K} b={b}: rel err {e:.2e}")
+        assert e <= (2e-6 if prec == bd.GRAM_BF16X6 else TOL)
+        assert np.array_equal(A[b], A[b].conj().T)
+        assert np.all(A[b].diagonal().imag == 0)
+    np.testing.assert_array_equal(diag.cpu().numpy(), A.diagonal(axis1=1, axis2=2).real.astype(np.float32))
+
+
 def test_gram_batch_zero_is_noop(torch, sess):
     H = torch.zeros((0, 4, 8), dtype=torch.complex64, device="cuda")
     A = bd.jacpcg_gram(sess, H, 1.0)
@@ -170,14 +193,17 @@ RZF_CASES = [("single", "literal", 1), ("single", "normalised", 1), ("batched", 
              ("batched", "normalised", 3)]
 
 
+@pytest.mark.parametrize("prec,flags", [(bd.GRAM_FP32, 0), (bd.GRAM_FP32, bd.EPILOGUE_FP32),
+                                        (bd.GRAM_BF16X6, 0)])
 @pytest.mark.parametrize("name,gain,n", RZF_CASES)
-def test_rzf_fixed_iterations(torch, sess, name, gain, n):
+def test_rzf_fixed_iterations(torch, sess, name, gain, n, prec, flags):
     w = workload(name, gain=gain)
     H = channel_batch(w, n=n)
     T = 8 if name == "batched" else 16
     for xi in w.xi_values():
         X = torch.empty((n, w.K, w.K), dtype=torch.complex64, device="cuda")
-        W, st, rc = bd.rzf_precoder(sess, dev(torch, H), xi, power=1.0, tol=0.0, max_iter=T, X_out=X, stats=True)
+        W, st, rc = bd.rzf_precoder(sess, dev(torch, H), xi, power=1.0, tol=0.0, max_iter=T, X_out=X, stats=True,
+                                    precision=prec, flags=flags)
         # T iterations unless the FP32 recurrence residual reached exactly zero earlier
         assert rc == bd.OK and 1 <= st["max_iters"] <= T
         Wn, Xn = W.cpu().numpy(), X.cpu().numpy()
@@ -186,7 +212,8 @@ def test_rzf_fixed_iterations(torch, sess, name, gain, n):
             ref = oracle.rzf(Hb, xi, tol=0.0, max_iter=T)
             ex, ew = rel(Xn[b].T, ref["X"]), rel(Wn[b].T, ref["W"])
             _, Wstar, _ = oracle.direct_rzf(Hb, xi)
-            print(f"{name}/{gain} xi={xi:g} b={b}: err X {ex:.2e} W {ew:.2e}; W vs FP64 direct {rel(Wn[b].T, Wstar):.2e}")
+            print(f"{name}/{gain} prec={prec} flags={flags} xi={xi:g} b={b}: err X {ex:.2e} W {ew:.2e}; "
+                  f"W vs FP64 direct {rel(Wn[b].T, Wstar):.2e}")
             assert ex <= TOL and ew <= TOL
             assert abs(np.linalg.norm(Wn[b]) ** 2 - 1.0) <= 1e-5
 
