@@ -47,13 +47,37 @@ def parse():
     return ap.parse_args()
 
 
-def algorithmic(M, K, n, T, batch):
-    """Useful flops and bytes per launch of each kernel."""
+PEAK_BF16_MFMA_TFLOPS = 2500.0    # MI355X dense BF16 matrix peak
+
+
+def algorithmic(M, K, n, T, batch, gram, epilogue):
+    """Per launch: algorithmic flops and HBM bytes of each kernel, and the work
+    its instructions actually execute on the matrix cores.
+
+    Split-BF16 kernels execute `products` bf16 MFMA products per FP32 product
+    (3 for hi+lo, 6 for the exact three-part split)."""
+    kp = -(-K // 32) * 32
+    gram_products = {"fp32": 1, "bf16x3": 3, "bf16x6": 6}[gram]
+    ep_products = 6 if epilogue == "split" else 1
     return {
-        "gram": dict(flops=batch * 4.0 * M * K * (K + 1), bytes=batch * (8.0 * M * K + 8.0 * K * K)),
-        "solve": dict(flops=batch * T * 8.0 * K * K * n, bytes=batch * (8.0 * K * K + 8.0 * K * n)),
-        "epilogue": dict(flops=batch * 8.0 * M * K * n, bytes=batch * (8.0 * M * K + 8.0 * K * n + 8.0 * M * n)),
+        "gram": dict(flops=batch * 4.0 * M * K * (K + 1), bytes=batch * (8.0 * M * K + 8.0 * K * K),
+                     exec_flops=batch * 8.0 * M * kp * (kp + 32) / 2 * gram_products,
+                     dtype="fp32" if gram == "fp32" else "bf16"),
+        "solve": dict(flops=batch * T * 8.0 * K * K * n, bytes=batch * (8.0 * K * K + 8.0 * K * n),
+                      exec_flops=batch * (T + 1) * 8.0 * kp * kp * n, dtype="fp32"),
+        "epilogue": dict(flops=batch * 8.0 * M * K * n, bytes=batch * (8.0 * M * K + 8.0 * K * n + 8.0 * M * n),
+                         exec_flops=batch * 8.0 * M * kp * n * ep_products,
+                         dtype="fp32" if epilogue == "fp32" else "bf16"),
     }
+
+
+def binding_roof(k):
+    """The roof that bounds a kernel: HBM time of its algorithmic bytes or the
+    matrix-core time of the work it executes, whichever is longer."""
+    peak = PEAK_FP32_MFMA_TFLOPS if k["dtype"] == "fp32" else PEAK_BF16_MFMA_TFLOPS
+    t_hbm = k["bytes"] / (PEAK_HBM_GBS * 1e9)
+    t_mma = k["exec_flops"] / (peak * 1e12)
+    return ("hbm", t_hbm) if t_hbm >= t_mma else ("mfma", t_mma)
 
 
 def traffic_for(kernel_phase):
@@ -159,24 +183,31 @@ def main():
         plain_value = batch / (plain_ms / 1e3)
         same = float(torch.linalg.vector_norm(W - W_plain) / torch.linalg.vector_norm(W_plain))
 
-    # roofline of the dominant kernel
-    alg = algorithmic(M, K, K, T, batch)
+    # roofline of the dominant kernel (and the binding roof of every kernel)
+    alg = algorithmic(M, K, K, T, batch, a.gram, a.epilogue)
     per_launch = {k: (phases[k][0] / phases[k][1]) if phases[k][1] else 0.0 for k in ("gram", "solve", "epilogue")}
-    dom = max(per_launch, key=per_launch.get)
-    dur_s = per_launch[dom] / 1e3
-    achieved = alg[dom]["flops"] / dur_s / 1e12
-    tr = traffic_for(dom)
-    roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP32_MFMA_TFLOPS, 4), "traffic": tr, "kernel": dom,
-                "avg_launch_us": round(per_launch[dom] * 1e3, 2)}
     kernels = {}
     for k in ("gram", "solve", "epilogue"):
         d = per_launch[k] / 1e3
-        if d > 0:
-            kernels[k] = {"us": round(per_launch[k] * 1e3, 2),
-                          "tflops": round(alg[k]["flops"] / d / 1e12, 2),
-                          "frac_fp32_mfma": round(alg[k]["flops"] / d / 1e12 / PEAK_FP32_MFMA_TFLOPS, 4),
-                          "alg_GBs": round(alg[k]["bytes"] / d / 1e9, 1)}
+        if d <= 0:
+            continue
+        bound, t_roof = binding_roof(alg[k])
+        kernels[k] = {"us": round(per_launch[k] * 1e3, 2), "bound": bound,
+                      "roof_us": round(t_roof * 1e6, 1), "frac_of_roof": round(t_roof / d, 4),
+                      "alg_tflops": round(alg[k]["flops"] / d / 1e12, 2),
+                      "alg_GBs": round(alg[k]["bytes"] / d / 1e9, 1),
+                      "mfma_dtype": alg[k]["dtype"]}
+    dom = max(per_launch, key=per_launch.get)
+    dur_s = per_launch[dom] / 1e3
+    bound, _ = binding_roof(alg[dom])
+    if bound == "hbm":
+        achieved, peak, unit = alg[dom]["bytes"] / dur_s / 1e9, PEAK_HBM_GBS, "GB/s"
+    else:
+        pk = PEAK_FP32_MFMA_TFLOPS if alg[dom]["dtype"] == "fp32" else PEAK_BF16_MFMA_TFLOPS
+        achieved, peak, unit = alg[dom]["flops"] / dur_s / 1e12, pk, "TFLOP/s"
+    roofline = {"bound": bound, "achieved": round(achieved, 2), "peak": peak, "unit": unit,
+                "frac": round(achieved / peak, 4), "traffic": traffic_for(dom), "kernel": dom,
+                "avg_launch_us": round(per_launch[dom] * 1e3, 2)}
 
     cpu, err_T, err_64 = (None, None, None)
     if not a.no_cpu:
