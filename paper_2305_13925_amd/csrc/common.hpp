@@ -82,6 +82,7 @@ struct PrecoderLaunch {
   float power;
   float* beta_out;                          // batch (nullable)
   int split;                                // 0: FP32 MFMA; 3: split-BF16 (3 parts, six products)
+  const double* fpart64; int ncb64;         // nullable: FP64 ||H X||^2 partials (refined path)
 };
 
 struct Gram64Launch {
@@ -92,19 +93,22 @@ struct Gram64Launch {
 };
 
 struct ResidualLaunch {
-  const double2* A64;                       // batch x K x K, ld K
-  const double2* X64;                       // batch x K x n col-major, ld K
+  const double2* A64;                       // batch x K x K row-major, ld K
+  const double2* X64;                       // batch x nrhs x K (column-major K x nrhs, ld K)
+  const float2* B; int64_t ldb, ldb_stride; // right-hand sides; NULL => identity
   int batch, K, nrhs;
-  float2* R32;                              // scaled residual, col-major ld K (next RHS)
-  float* scale;                             // batch x n: ||r_j|| used to scale R32
-  double* rnorm2;                           // batch: ||R||_F^2
+  double xi;
+  float2* R32;                              // batch x nrhs x K: r_j / ||r_j|| (next correction RHS)
+  double* scale;                            // batch x nrhs: ||r_j||
+  double* rnorm2;                           // per workgroup: sum_j ||r_j||^2
+  double* quad;                             // per workgroup: sum_j Re x_j^H (A64 - xi I) x_j
 };
 
 struct AccumulateLaunch {
-  double2* X64; const float2* E; const float* scale;
+  double2* X64; const float2* E; const double* scale;
   int batch, K, nrhs;
-  int first;                                // X64 = E * scale instead of +=
-  float2* X32;                              // nullable: rounded copy
+  int first;                                // X64 = E instead of X64 += scale * E
+  float2* X32;                              // nullable: rounded copy of the result
 };
 
 // Kernel launchers (defined in the .hip files). All return hipError_t of the
@@ -118,6 +122,7 @@ hipError_t launch_precoder(const PrecoderLaunch& e, hipStream_t s);
 hipError_t launch_gram64(const Gram64Launch& g, hipStream_t s);
 hipError_t launch_residual(const ResidualLaunch& r, hipStream_t s);
 hipError_t launch_accumulate(const AccumulateLaunch& a, hipStream_t s);
+int residual_workgroups_per_instance(int nrhs);
 hipError_t launch_widen(const float2* X, int64_t ldx, int64_t stride_x, int batch, int K, int n,
                         double2* out, hipStream_t s);
 

@@ -16,6 +16,19 @@
 namespace jacpcg {
 namespace {
 
+// beta_pow = sqrt(P / ||H X||_F^2) from the per-workgroup partial sums of the
+// solve (fixed order); 0 when H X = 0.
+__device__ __forceinline__ float power_factor(const PrecoderLaunch& e, int b) {
+  if (e.fpart64) {
+    double fs = 0.0;
+    for (int c = 0; c < e.ncb64; ++c) fs += e.fpart64[(int64_t)b * e.ncb64 + c];
+    return fs > 0.0 ? (float)sqrt((double)e.power / fs) : 0.f;
+  }
+  float fs = 0.f;
+  for (int c = 0; c < e.ncb; ++c) fs += e.fpart[(int64_t)b * e.ncb + c];
+  return fs > 0.f ? sqrtf(e.power / fs) : 0.f;
+}
+
 template <int KT, int NJ, bool VEC>
 __global__ __launch_bounds__(256) void precoder_f32_kernel(PrecoderLaunch e) {
   constexpr int KP = KT * 32;
@@ -34,9 +47,7 @@ __global__ __launch_bounds__(256) void precoder_f32_kernel(PrecoderLaunch e) {
 
   __shared__ float2 Xs[KP][NC];
 
-  float fs = 0.f;
-  for (int c = 0; c < e.ncb; ++c) fs += e.fpart[(int64_t)b * e.ncb + c];
-  const float beta = fs > 0.f ? sqrtf(e.power / fs) : 0.f;
+  const float beta = power_factor(e, b);
   if (e.beta_out && mb == 0 && cw == 0 && threadIdx.x == 0) e.beta_out[b] = beta;
 
   const float2* Xb = e.X + (int64_t)b * e.stride_x;
@@ -165,9 +176,7 @@ __global__ __launch_bounds__(256) void precoder_bf16_kernel(PrecoderLaunch e) {
     return xs_dyn[(((size_t)plane * NS + s) * K8 + k8) * NC + j];
   };
 
-  float fs = 0.f;
-  for (int c = 0; c < e.ncb; ++c) fs += e.fpart[(int64_t)b * e.ncb + c];
-  const float beta = fs > 0.f ? sqrtf(e.power / fs) : 0.f;
+  const float beta = power_factor(e, b);
   if (e.beta_out && mb == 0 && cw == 0 && threadIdx.x == 0) e.beta_out[b] = beta;
 
   const float2* Xb = e.X + (int64_t)b * e.stride_x;

@@ -9,6 +9,8 @@ using namespace jacpcg;
 
 namespace {
 
+constexpr int kMaxRefineSteps = 16;
+
 int hip_error(jacpcg_session* s, hipError_t e, const char* what) {
   s->poisoned = true;
   std::string m = std::string(what) + ": " + hipGetErrorString(e);
@@ -107,8 +109,6 @@ int jacpcg_session::run_rzf(hipStream_t st, int batch, int M, int K, const float
                             bool precond_none, bool split_epilogue, double refine_tol, float2* W, int64_t ldw,
                             int64_t stride_w,
                             float2* X_out, double2* X64_out, jacpcg_stats* stats) {
-  (void)refine_tol;
-  if (refine) return set_error(JACPCG_E_UNSUPPORTED, "FP64 refinement not available in this build");
   const int ncb = (K + 31) / 32;
   const size_t KK = (size_t)K * K;
   Workspace ws;
@@ -121,8 +121,16 @@ int jacpcg_session::run_rzf(hipStream_t st, int batch, int M, int K, const float
   const size_t oI = ws.take<int32_t>((size_t)batch * K);
   const size_t oR = ws.take<float>((size_t)batch * K);
   const size_t oB = ws.take<float>(batch);
-  const size_t oX64 = X64_out ? 0 : 0;
-  (void)oX64;
+  // refinement buffers
+  const int n16 = residual_workgroups_per_instance(K);
+  const size_t oA64 = refine ? ws.take<double2>(batch * KK) : 0;
+  const size_t oX64 = refine ? ws.take<double2>(batch * KK) : 0;
+  const size_t oR32 = refine ? ws.take<float2>(batch * KK) : 0;
+  const size_t oE32 = refine ? ws.take<float2>(batch * KK) : 0;
+  const size_t oSc = refine ? ws.take<double>(batch * (size_t)K) : 0;
+  const size_t oRn = refine ? ws.take<double>((size_t)batch * n16) : 0;
+  const size_t oQd = refine ? ws.take<double>((size_t)batch * n16) : 0;
+  const size_t oWG2 = refine ? ws.take<int32_t>((size_t)batch * ncb) : 0;
   if (int rc = reserve(ws)) return rc;
   float2* A = at<float2>(oA);
   float* gdiag = at<float>(oG);
@@ -177,6 +185,65 @@ int jacpcg_session::run_rzf(hipStream_t st, int batch, int M, int K, const float
   e = launch_status_reduce(wgs, ncb, batch, status, st);
   if (e != hipSuccess) return hip_error(this, e, "status reduce launch");
 
+  // ---- FP64-residual iterative refinement (B = I) --------------------------
+  int refine_steps = 0;
+  double refine_res = 0.0;
+  double2* X64 = refine ? at<double2>(oX64) : nullptr;
+  double* quad = refine ? at<double>(oQd) : nullptr;
+  if (refine) {
+    double2* A64 = at<double2>(oA64);
+    float2* R32 = at<float2>(oR32);
+    float2* E32 = at<float2>(oE32);
+    double* scale = at<double>(oSc);
+    double* rn2 = at<double>(oRn);
+    Gram64Launch g64{H, ldh, stride_h, batch, M, K, xi, A64};
+    e = timed(st, JACPCG_PHASE_GRAM64, [&] { return launch_gram64(g64, st); });
+    if (e != hipSuccess) return hip_error(this, e, "gram64 launch");
+    AccumulateLaunch acc{X64, X, nullptr, batch, K, K, 1, nullptr};
+    e = launch_accumulate(acc, st);  // X64 = X (exact widening)
+    if (e != hipSuccess) return hip_error(this, e, "accumulate launch");
+    double* h_rn = (double*)host_scratch((size_t)batch * n16 * sizeof(double));
+    if (!h_rn) return set_error(JACPCG_E_OUT_OF_MEMORY, "pinned host staging allocation failed");
+    for (int step = 0;; ++step) {
+      ResidualLaunch rl{A64, X64, nullptr, 0, 0, batch, K, K, xi, R32, scale, rn2, quad};
+      e = timed(st, JACPCG_PHASE_RESIDUAL, [&] { return launch_residual(rl, st); });
+      if (e != hipSuccess) return hip_error(this, e, "residual launch");
+      S_HIP(hipMemcpyAsync(h_rn, rn2, (size_t)batch * n16 * sizeof(double), hipMemcpyDeviceToHost, st));
+      S_HIP(hipStreamSynchronize(st));
+      refine_res = 0.0;
+      for (int b = 0; b < batch; ++b) {
+        double f = 0.0;
+        for (int c = 0; c < n16; ++c) f += h_rn[(size_t)b * n16 + c];
+        refine_res = std::max(refine_res, std::sqrt(f / K));  // ||R||_F / ||I||_F
+      }
+      if (refine_res <= refine_tol || step >= kMaxRefineSteps) break;
+      // correction: A E = R / ||r_j|| column by column, in FP32
+      PcgLaunch pc{};
+      pc.A = A;
+      pc.lda = K;
+      pc.stride_a = (int64_t)KK;
+      pc.B = R32;
+      pc.ldb = K;
+      pc.stride_b = (int64_t)KK;
+      pc.X = E32;
+      pc.ldx = K;
+      pc.stride_x = (int64_t)KK;
+      pc.batch = batch;
+      pc.K = K;
+      pc.nrhs = K;
+      pc.tol = (float)tol;
+      pc.max_iter = max_iter;
+      pc.precond_none = precond_none;
+      pc.wg_status = at<int32_t>(oWG2);
+      e = timed(st, JACPCG_PHASE_SOLVE, [&] { return launch_pcg(pc, st, nullptr); });
+      if (e != hipSuccess) return hip_error(this, e, "correction pcg launch");
+      AccumulateLaunch ac{X64, E32, scale, batch, K, K, 0, X};
+      e = launch_accumulate(ac, st);
+      if (e != hipSuccess) return hip_error(this, e, "accumulate launch");
+      ++refine_steps;
+    }
+  }
+
   PrecoderLaunch E{};
   E.H = H;
   E.ldh = ldh;
@@ -196,14 +263,21 @@ int jacpcg_session::run_rzf(hipStream_t st, int batch, int M, int K, const float
   E.power = (float)power;
   E.beta_out = beta;
   E.split = split_epilogue ? 3 : 0;
+  E.fpart64 = quad;  // refined path: ||H X64||^2 from the last FP64 residual
+  E.ncb64 = n16;
   e = timed(st, JACPCG_PHASE_EPILOGUE, [&] { return launch_precoder(E, st); });
   if (e != hipSuccess) return hip_error(this, e, "precoder launch");
 
   if (X64_out) {
-    e = launch_widen(X, K, (int64_t)KK, batch, K, K, X64_out, st);
-    if (e != hipSuccess) return hip_error(this, e, "widen launch");
+    if (refine)
+      e = hipMemcpyAsync(X64_out, X64, batch * KK * sizeof(double2), hipMemcpyDeviceToDevice, st);
+    else
+      e = launch_widen(X, K, (int64_t)KK, batch, K, K, X64_out, st);
+    if (e != hipSuccess) return hip_error(this, e, "X64 output");
   }
 
+  jacpcg_stats local_stats;
+  if (!stats && refine) stats = &local_stats;  // the refined path synchronises anyway
   if (!stats) return JACPCG_OK;
   const size_t hb = (size_t)batch * K * 8 + (size_t)batch * 8;
   char* h = (char*)host_scratch(hb);
@@ -218,6 +292,9 @@ int jacpcg_session::run_rzf(hipStream_t st, int batch, int M, int K, const float
   S_HIP(hipMemcpyAsync(h_b, beta, (size_t)batch * 4, hipMemcpyDeviceToHost, st));
   S_HIP(hipStreamSynchronize(st));
   fill_stats_host(stats, batch, K, h_it, h_rr, h_st, h_b);
+  stats->refine_steps = refine_steps;
+  stats->max_refine_residual = refine_res;
+  if (refine && refine_res > refine_tol && stats->worst_status == JACPCG_OK) stats->worst_status = JACPCG_NOT_CONVERGED;
   return stats->worst_status;
 }
 

@@ -305,3 +305,65 @@ def test_full_size_sampled(torch, sess, name, T, samples):
         e = rel(Wn[b].T, ref["W"])
         print(f"{name} b={b}: W err {e:.2e}")
         assert e <= TOL
+
+
+# ---------------------------------------------------------------------------
+# FP64-residual iterative refinement: X64 against the exact (FP64 Cholesky)
+# inverse at 1e-10.
+REFINE_TOL = 1e-10
+
+
+@pytest.mark.parametrize("prec", [bd.GRAM_FP32, bd.GRAM_BF16X3, bd.GRAM_BF16X6])
+@pytest.mark.parametrize("name,gain,n,tol,T", [("precision", "normalised", 2, 1e-6, 64),
+                                               ("precision", "literal", 2, 0.0, 16),
+                                               ("batched", "normalised", 3, 1e-5, 32)])
+def test_refined_reaches_fp64(torch, sess, prec, name, gain, n, tol, T):
+    w = workload(name, gain=gain)
+    H = channel_batch(w, n=n)
+    xi = w.xi_values()[-1]
+    X64 = torch.empty((n, w.K, w.K), dtype=torch.complex128, device="cuda")
+    W, st, rc = bd.rzf_precoder(sess, dev(torch, H), xi, tol=tol, max_iter=T, precision=prec | bd.REFINE_FP64,
+                                refine_tol=REFINE_TOL, X64_out=X64, stats=True)
+    assert rc == bd.OK, st
+    assert st["max_refine_residual"] <= REFINE_TOL and st["refine_steps"] >= 1
+    Xn, Wn = X64.cpu().numpy(), W.cpu().numpy()
+    for b in range(n):
+        Xs, Ws, _ = oracle.direct_rzf(H[b].T.astype(np.complex128), xi)
+        ex, ew = rel(Xn[b].T, Xs), rel(Wn[b].T, Ws)
+        print(f"refined {name}/{gain} prec={prec} b={b}: steps {st['refine_steps']} X64 err {ex:.2e} W err {ew:.2e}")
+        assert ex <= REFINE_TOL
+        assert ew <= 1e-6          # W is complex64: only its rounding remains
+
+
+def test_refined_stress_sampled(torch, sess):
+    # Near-ZF regularisation, strong correlation: ill-conditioned systems.
+    w = workload("stress")
+    H = channel_batch(w, n=2)
+    X64 = torch.empty((2, w.K, w.K), dtype=torch.complex128, device="cuda")
+    W, st, rc = bd.rzf_precoder(sess, dev(torch, H), w.xi, tol=1e-6, max_iter=1024,
+                                precision=bd.GRAM_FP32 | bd.REFINE_FP64, refine_tol=REFINE_TOL, X64_out=X64,
+                                stats=True)
+    assert rc == bd.OK, st
+    Xn = X64.cpu().numpy()
+    for b in range(2):
+        A = oracle.gram(H[b].T.astype(np.complex128), w.xi)
+        Xs = oracle.chol_inverse(A)
+        e = rel(Xn[b].T, Xs)
+        print(f"stress b={b}: cond {np.linalg.cond(A):.1e} PCG iters {st['max_iters']} refine steps "
+              f"{st['refine_steps']} X64 err {e:.2e}")
+        assert e <= REFINE_TOL
+
+
+def test_refined_full_size_precision_sampled(torch, sess):
+    w = workload("precision")
+    H = channel_batch(w)
+    xi = w.xi_values()[0]
+    X64 = torch.empty((w.batch, w.K, w.K), dtype=torch.complex128, device="cuda")
+    W, st, rc = bd.rzf_precoder(sess, dev(torch, H), xi, tol=1e-6, max_iter=64,
+                                precision=bd.GRAM_BF16X3 | bd.REFINE_FP64, refine_tol=REFINE_TOL, X64_out=X64,
+                                stats=True)
+    assert rc == bd.OK and st["max_refine_residual"] <= REFINE_TOL
+    Xn = X64.cpu().numpy()
+    for b in (0, 97, 255):
+        Xs, _, _ = oracle.direct_rzf(H[b].T.astype(np.complex128), xi)
+        assert rel(Xn[b].T, Xs) <= REFINE_TOL
