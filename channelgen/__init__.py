@@ -15,4 +15,5 @@ from .xlmimo import (  # noqa: F401
     serving_requests,
     request_channels,
     instance_matrix,
+    device_pool,
 )

@@ -182,3 +182,32 @@ def request_channels(req):
         out[b], _ = channel_instance(req["M"], req["S"], req["K"], req["r"], req["vr"],
                                      req["seed"], b)
     return out
+
+
+def device_pool(M, S, K, r, vr, n, seed, device="cuda", gain="literal"):
+    """n instances of the same channel model drawn with torch on a device
+    (complex64 [n, K, M]), for workloads too large to draw on the host (the
+    serving stream). Same law as ``channel_instance``; a different stream of
+    random numbers (torch's generator seeded with `seed`)."""
+    import torch
+    if M % S:
+        raise ValueError("M must be a multiple of S")
+    Ms = M // S
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    d = torch.rand((n, K), generator=g, device=device, dtype=torch.float64) * 90.0 + 10.0
+    lo, hi = int(vr[0]), min(int(vr[1]), S)
+    lo = max(1, min(lo, hi))
+    vr_len = torch.randint(lo, hi + 1, (n, K), generator=g, device=device)
+    start = (torch.rand((n, K), generator=g, device=device, dtype=torch.float64)
+             * (S - vr_len + 1).to(torch.float64)).floor().to(torch.int64)
+    sub = torch.arange(S, device=device)
+    mask = (sub[None, None, :] >= start[..., None]) & (sub[None, None, :] < (start + vr_len)[..., None])
+    re = torch.randn((n, K, S, Ms), generator=g, device=device, dtype=torch.float64)
+    im = torch.randn((n, K, S, Ms), generator=g, device=device, dtype=torch.float64)
+    L = torch.as_tensor(_ar1_factor(Ms, r), device=device)
+    y = torch.complex(re @ L.T, im @ L.T) / (2.0 ** 0.5)
+    y = y * mask[..., None]
+    beta = d ** -3.7 if gain == "literal" else (d / 10.0) ** -3.7
+    h = (beta.sqrt()[..., None, None] * y).reshape(n, K, M)
+    return h.to(torch.complex64).contiguous()

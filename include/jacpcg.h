@@ -146,8 +146,8 @@ int jacpcg_gram(jacpcg_session* s, void* stream, int batch, int M, int K,
  * tol > 0: column j stops after the first iteration with
  *   ||r_j||_2 <= tol * ||b_j||_2 (recurrence residual; Step 2's rule made
  *   relative); tol == 0 runs exactly max_iter iterations (a column whose
- *   residual underflows to exactly zero stops early). One iteration = one A p
- *   product.
+ *   residual falls below 2^-40 ||b_j||, where an FP32 iterate no longer
+ *   changes, stops early as converged). One iteration = one A p product.
  * flags: JACPCG_PRECOND_JACOBI (default) or JACPCG_PRECOND_NONE (plain CG).
  * iters (nullable, batch x nrhs int32): iterations done per column.
  * relres (nullable, batch x nrhs float): ||r_j|| / ||b_j|| at the stop.
@@ -206,6 +206,64 @@ int rzf_precoder_plain(jacpcg_session* s, void* stream, int batch, int M, int K,
                        double xi, double power, double tol, int max_iter, int flags,
                        jacpcg_c64* W, int64_t ldw, int64_t stride_w,
                        jacpcg_c64* X_out, jacpcg_stats* stats);
+
+/* ---- request API: continuous batching ---------------------------------- */
+
+/* One precoder request: n_sub subcarrier instances of one (M, K) shape, each
+ * solved as rzf_precoder would (B = I_K; Gram precision JACPCG_GRAM_*, no
+ * refinement; flags JACPCG_PRECOND_* | JACPCG_EPILOGUE_FP32).
+ * H: device, n_sub instances of column-major M x K complex64 (ld M, stride
+ * M*K). W: device output of the same layout. Both buffers are owned by the
+ * caller and must stay alive until jacpcg_poll / jacpcg_wait returns a final
+ * result for the request. */
+typedef struct {
+  int M, K, n_sub;
+  const jacpcg_c64* H;
+  jacpcg_c64* W;
+  double xi, power, tol;
+  int max_iter, precision, flags;
+  uint64_t user_tag;
+} jacpcg_request;
+
+/* Result of a request. status: the request's worst per-instance status (OK,
+ * NOT_CONVERGED, E_BREAKDOWN), E_CANCELLED, E_HIP, or NOT_READY while in flight.
+ * Times are microseconds of the session clock (jacpcg_session_clock_us):
+ * submission, admission (launch of its batch) and completion as observed by
+ * the session. */
+typedef struct {
+  int status;
+  int32_t max_iters;
+  double t_submit_us, t_admit_us, t_done_us;
+  uint64_t user_tag;
+} jacpcg_result;
+
+/* Queue a request; returns a ticket. The session's scheduler admits requests
+ * in FIFO order while its HBM budget (H + W + workspace of the admitted
+ * requests) and in-flight batch slots allow, batches admitted requests of the
+ * same shape and settings into one launch, and runs batches of different slots
+ * concurrently. A request's result does not depend on what it is batched with.
+ * Errors: E_INVALID_ARG (sizes, NULL buffers, xi < 0, power <= 0, tol < 0,
+ * max_iter < 0, unknown flags), E_UNSUPPORTED (refinement requested),
+ * E_BUDGET (the request alone needs more than the session budget). */
+int jacpcg_submit(jacpcg_session* s, const jacpcg_request* r, uint64_t* ticket);
+
+/* Non-blocking: NOT_READY while the request is queued or running; OK once final
+ * (the result is then in *out and the ticket is released). E_INVALID_ARG for an
+ * unknown or already collected ticket. */
+int jacpcg_poll(jacpcg_session* s, uint64_t ticket, jacpcg_result* out);
+
+/* Block until the request is final (timeout_ms < 0: no limit). OK with the
+ * result in *out (ticket released), or E_TIMEOUT (ticket kept). */
+int jacpcg_wait(jacpcg_session* s, uint64_t ticket, int timeout_ms, jacpcg_result* out);
+
+/* Cancel: a queued request is removed and completes with E_CANCELLED; a
+ * running one still finishes on the device (W may be written) and reports
+ * E_CANCELLED. A completed request is unaffected. */
+int jacpcg_cancel(jacpcg_session* s, uint64_t ticket);
+
+/* Microseconds since the session was created (steady clock); the clock of the
+ * request timestamps. */
+double jacpcg_session_clock_us(jacpcg_session* s);
 
 #ifdef __cplusplus
 }

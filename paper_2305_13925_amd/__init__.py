@@ -11,6 +11,11 @@ from .binding import (  # noqa: F401
     jacpcg_solve,
     rzf_precoder,
     rzf_precoder_plain,
+    jacpcg_submit,
+    jacpcg_poll,
+    jacpcg_wait,
+    jacpcg_cancel,
+    jacpcg_session_clock_us,
     lib,
     status_string,
     last_error,

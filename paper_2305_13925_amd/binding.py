@@ -66,6 +66,20 @@ class JacpcgStats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
+class JacpcgRequest(C.Structure):
+    _fields_ = [("M", C.c_int), ("K", C.c_int), ("n_sub", C.c_int), ("H", C.c_void_p), ("W", C.c_void_p),
+                ("xi", C.c_double), ("power", C.c_double), ("tol", C.c_double), ("max_iter", C.c_int),
+                ("precision", C.c_int), ("flags", C.c_int), ("user_tag", C.c_uint64)]
+
+
+class JacpcgResult(C.Structure):
+    _fields_ = [("status", C.c_int), ("max_iters", C.c_int32), ("t_submit_us", C.c_double),
+                ("t_admit_us", C.c_double), ("t_done_us", C.c_double), ("user_tag", C.c_uint64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class JacpcgError(RuntimeError):
     def __init__(self, code, message):
         super().__init__(f"{status_string(code)} ({code}): {message}")
@@ -95,18 +109,34 @@ def _declare(lib):
     lib.rzf_precoder_plain.argtypes = [_vp, _vp, C.c_int, C.c_int, C.c_int, _vp, _i64, _i64, C.c_double,
                                        C.c_double, C.c_double, C.c_int, C.c_int, _vp, _i64, _i64, _vp,
                                        C.POINTER(JacpcgStats)]
+    lib.jacpcg_submit.argtypes = [_vp, C.POINTER(JacpcgRequest), C.POINTER(C.c_uint64)]
+    lib.jacpcg_poll.argtypes = [_vp, C.c_uint64, C.POINTER(JacpcgResult)]
+    lib.jacpcg_wait.argtypes = [_vp, C.c_uint64, C.c_int, C.POINTER(JacpcgResult)]
+    lib.jacpcg_cancel.argtypes = [_vp, C.c_uint64]
+    lib.jacpcg_session_clock_us.argtypes = [_vp]
+    lib.jacpcg_session_clock_us.restype = C.c_double
     for name in ("jacpcg_session_create", "jacpcg_session_set_profiling", "jacpcg_session_phase_times",
-                 "jacpcg_gram", "jacpcg_solve", "rzf_precoder", "rzf_precoder_plain"):
+                 "jacpcg_gram", "jacpcg_solve", "rzf_precoder", "rzf_precoder_plain", "jacpcg_submit",
+                 "jacpcg_poll", "jacpcg_wait", "jacpcg_cancel"):
         getattr(lib, name).restype = C.c_int
     return lib
 
 
 def lib():
-    """The loaded library (raises if it has not been built)."""
+    """The loaded library (raises if it has not been built).
+
+    torch is imported first: torch ships its own HIP runtime under the same
+    soname (libamdhip64.so.7), and whichever copy is loaded first serves the
+    whole process. Loading torch's first keeps one HIP runtime for torch's
+    allocations and streams and this library's kernels."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2305_13925_amd.build`")
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         _lib = _declare(C.CDLL(LIB_PATH))
     return _lib
 
@@ -277,6 +307,43 @@ def rzf_precoder_plain(session, H, xi, power=1.0, tol=0.0, max_iter=16, flags=PR
     if stats:
         return W, st.as_dict(), rc
     return W
+
+
+def jacpcg_submit(session, H, W, xi, power=1.0, tol=0.0, max_iter=16, precision=GRAM_FP32, flags=PRECOND_JACOBI,
+                  user_tag=0):
+    """Queue a request: H, W complex64 [n_sub, K, M] device tensors (kept alive
+    by the caller until the result is collected). Returns the ticket."""
+    torch = _torch()
+    _require(H, "H", torch.complex64)
+    n_sub, K, M = H.shape
+    _require(W, "W", torch.complex64, (n_sub, K, M))
+    r = JacpcgRequest(M, K, n_sub, H.data_ptr(), W.data_ptr(), float(xi), float(power), float(tol), int(max_iter),
+                      int(precision), int(flags), int(user_tag))
+    t = C.c_uint64()
+    _check(lib().jacpcg_submit(session.handle, C.byref(r), C.byref(t)))
+    return t.value
+
+
+def jacpcg_poll(session, ticket):
+    """(rc, result dict): rc NOT_READY while in flight, OK when final."""
+    res = JacpcgResult()
+    rc = _check(lib().jacpcg_poll(session.handle, int(ticket), C.byref(res)))
+    return rc, res.as_dict()
+
+
+def jacpcg_wait(session, ticket, timeout_ms=-1):
+    """Result dict of a final request; raises JacpcgError(E_TIMEOUT) on timeout."""
+    res = JacpcgResult()
+    _check(lib().jacpcg_wait(session.handle, int(ticket), int(timeout_ms), C.byref(res)))
+    return res.as_dict()
+
+
+def jacpcg_cancel(session, ticket):
+    _check(lib().jacpcg_cancel(session.handle, int(ticket)))
+
+
+def jacpcg_session_clock_us(session):
+    return lib().jacpcg_session_clock_us(session.handle)
 
 
 def exported_symbols():

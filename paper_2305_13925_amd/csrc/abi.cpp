@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <chrono>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -325,6 +326,43 @@ int rzf_precoder_plain(jacpcg_session* s, void* stream, int batch, int M, int K,
   return s->run_rzf_plain((hipStream_t)stream, batch, M, K, (const float2*)H, ldh, stride_h, xi, power, tol,
                           max_iter, (flags & JACPCG_PRECOND_NONE) != 0, (flags & JACPCG_EPILOGUE_FP32) == 0,
                           (float2*)W, ldw, stride_w, (float2*)X_out, stats);
+}
+
+double jacpcg_session_clock_us(jacpcg_session* s) {
+  if (!s) return 0.0;
+  return std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - s->t0).count();
+}
+
+int jacpcg_submit(jacpcg_session* s, const jacpcg_request* r, uint64_t* ticket) {
+  JP_CHECK(r != nullptr, "request is NULL");
+  JP_CHECK(ticket != nullptr, "ticket is NULL");
+  int rc = check_session(s);
+  if (rc) return rc;
+  if (!s->sched) s->sched.reset(new Scheduler(s));
+  return s->sched->submit(*r, ticket);
+}
+
+int jacpcg_poll(jacpcg_session* s, uint64_t ticket, jacpcg_result* out) {
+  JP_CHECK(out != nullptr, "result is NULL");
+  int rc = check_session(s);
+  if (rc) return rc;
+  if (!s->sched) return fail(JACPCG_E_INVALID_ARG, "unknown ticket %llu", (unsigned long long)ticket);
+  return s->sched->poll(ticket, out);
+}
+
+int jacpcg_wait(jacpcg_session* s, uint64_t ticket, int timeout_ms, jacpcg_result* out) {
+  JP_CHECK(out != nullptr, "result is NULL");
+  int rc = check_session(s);
+  if (rc) return rc;
+  if (!s->sched) return fail(JACPCG_E_INVALID_ARG, "unknown ticket %llu", (unsigned long long)ticket);
+  return s->sched->wait(ticket, timeout_ms, out);
+}
+
+int jacpcg_cancel(jacpcg_session* s, uint64_t ticket) {
+  int rc = check_session(s);
+  if (rc) return rc;
+  if (!s->sched) return fail(JACPCG_E_INVALID_ARG, "unknown ticket %llu", (unsigned long long)ticket);
+  return s->sched->cancel(ticket);
 }
 
 }  // extern "C"

@@ -40,6 +40,7 @@ constexpr int kStatusBreakdown = -5;
 // ---------------------------------------------------------------------------
 struct GramLaunch {
   const float2* H; int64_t ldh, stride_h;
+  const float2* const* H_ptrs;  // nullable: per-instance channel pointers (ld ldh) instead of H + b * stride_h
   int batch, M, K;
   float xi;
   float2* A; int64_t lda, stride_a;
@@ -47,6 +48,7 @@ struct GramLaunch {
   float* gdiag;     // batch x K, diag(H^H H) without xi (nullable)
   int precision;    // 0 fp32, 1 bf16x3, 2 bf16x6
   int m_split;      // waves per workgroup that split the antenna range (tuned)
+  int no_vec;       // 1: some channel pointer or ldh does not allow 16-byte loads
 };
 
 // Per-workgroup resumable PCG state for chunked launches.
@@ -75,6 +77,8 @@ struct PcgLaunch {
 
 struct PrecoderLaunch {
   const float2* H; int64_t ldh, stride_h;
+  const float2* const* H_ptrs;  // nullable: per-instance channel pointers
+  float2* const* W_ptrs;        // nullable: per-instance precoder pointers (ld ldw)
   const float2* X; int64_t ldx, stride_x;
   float2* W; int64_t ldw, stride_w;
   int batch, M, K, nrhs;
@@ -83,6 +87,7 @@ struct PrecoderLaunch {
   float* beta_out;                          // batch (nullable)
   int split;                                // 0: FP32 MFMA; 3: split-BF16 (3 parts, six products)
   const double* fpart64; int ncb64;         // nullable: FP64 ||H X||^2 partials (refined path)
+  int no_vec;                               // 1: some precoder pointer or ldw does not allow 16-byte stores
 };
 
 struct Gram64Launch {

@@ -152,7 +152,7 @@ __global__ __launch_bounds__(512) void gram_f32_kernel(GramLaunch g) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nw = blockDim.x >> 6;
   const int half = lane >> 5, li = lane & 31;
-  const float2* Hb = g.H + (int64_t)b * g.stride_h;
+  const float2* Hb = g.H_ptrs ? g.H_ptrs[b] : g.H + (int64_t)b * g.stride_h;
   const int ui = ti * 32 + li, uj = tj * 32 + li;
   const bool vi = ui < g.K, vj = uj < g.K;
   const float2* hi = Hb + (int64_t)(vi ? ui : 0) * g.ldh;
@@ -206,7 +206,7 @@ __global__ __launch_bounds__(256) void gram_bf16_kernel(GramLaunch g) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nw = blockDim.x >> 6;
   const int half = lane >> 5, li = lane & 31;
-  const float2* Hb = g.H + (int64_t)b * g.stride_h;
+  const float2* Hb = g.H_ptrs ? g.H_ptrs[b] : g.H + (int64_t)b * g.stride_h;
   const int ui = ti * 32 + li;
   const bool vi = ui < g.K;
   const float2* hi = Hb + (int64_t)(vi ? ui : 0) * g.ldh;
@@ -311,7 +311,7 @@ __global__ __launch_bounds__(256) void gram_bf16_small_kernel(GramLaunch g) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nw = blockDim.x >> 6;
   const int half = lane >> 5, li = lane & 31;
-  const float2* Hb = g.H + (int64_t)b * g.stride_h;
+  const float2* Hb = g.H_ptrs ? g.H_ptrs[b] : g.H + (int64_t)b * g.stride_h;
   bool vu[NT];
   const float2* row[NT];
 #pragma unroll
@@ -323,7 +323,7 @@ __global__ __launch_bounds__(256) void gram_bf16_small_kernel(GramLaunch g) {
   const int chunk = ((g.M + nw * 16 - 1) / (nw * 16)) * 16;
   const int m0 = wave * chunk;
   const int m1 = min(g.M, m0 + chunk);
-  const bool vec = ((uintptr_t)g.H % 16 == 0) && (g.ldh % 2 == 0) && (g.stride_h % 2 == 0);
+  const bool vec = !g.no_vec && ((uintptr_t)g.H % 16 == 0) && (g.ldh % 2 == 0) && (g.stride_h % 2 == 0);
 
   floatx16 accR[NTILE], accI[NTILE];
 #pragma unroll
@@ -406,7 +406,7 @@ hipError_t launch_gram(const GramLaunch& g, hipStream_t s) {
   int waves = g.m_split > 0 ? g.m_split : 4;
   if (waves > kGramMaxWaves) waves = kGramMaxWaves;
   const dim3 block(64 * waves);
-  const bool vec = ((uintptr_t)g.H % 16 == 0) && (g.ldh % 2 == 0) && (g.stride_h % 2 == 0);
+  const bool vec = !g.no_vec && ((uintptr_t)g.H % 16 == 0) && (g.ldh % 2 == 0) && (g.stride_h % 2 == 0);
   const size_t lds = (size_t)waves * 2 * 16 * 64 * sizeof(float);
   if (g.precision == 0) {
     const dim3 grid((unsigned)(nt * (nt + 1) / 2 * g.batch));

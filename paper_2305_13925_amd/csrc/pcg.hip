@@ -204,7 +204,10 @@ __global__ __launch_bounds__(KT * 64) void pcg_f32_kernel(PcgLaunch p) {
 #pragma unroll
   for (int r = 0; r < 16; ++r) Psh[w * 32 + d32_row(r, half)][jl] = make_float2(pr[r], pim[r]);
 
-  const float tol2 = p.tol * p.tol;
+  // FP32 range guard: below ||r|| = 2^-40 ||b|| an FP32 iterate no longer
+  // changes (the update is far under its rounding) while p^H A p heads for
+  // underflow, so such a column ends as converged even with tol = 0.
+  const float tol2 = fmaxf(p.tol * p.tol, 0x1p-80f);
   const int tend = chunked ? min(p.max_iter, t0 + p.chunk) : p.max_iter;
   int t = t0;
   while (t < tend) {

@@ -68,7 +68,7 @@ __global__ __launch_bounds__(256) void precoder_f32_kernel(PrecoderLaunch e) {
   const int mrow = m0 + jl;
   const bool mvalid = mrow < e.M;
   const int klim = max(0, min(KH, K - half * KH));
-  const float2* hcol = e.H + (int64_t)b * e.stride_h + (int64_t)(half * KH) * e.ldh + (mvalid ? mrow : 0);
+  const float2* hcol = (e.H_ptrs ? e.H_ptrs[b] : e.H + (int64_t)b * e.stride_h) + (int64_t)(half * KH) * e.ldh + (mvalid ? mrow : 0);
 
   floatx16 wr[NJ], wi[NJ];
 #pragma unroll
@@ -96,7 +96,7 @@ __global__ __launch_bounds__(256) void precoder_f32_kernel(PrecoderLaunch e) {
     }
   }
 
-  float2* Wb = e.W + (int64_t)b * e.stride_w;
+  float2* Wb = (e.W_ptrs ? e.W_ptrs[b] : e.W + (int64_t)b * e.stride_w);
 #pragma unroll
   for (int t = 0; t < NJ; ++t) {
     const int j = cw * NC + t * 32 + jl;
@@ -121,7 +121,7 @@ __global__ __launch_bounds__(256) void precoder_f32_kernel(PrecoderLaunch e) {
 template <int KT>
 hipError_t launch_kt(const PrecoderLaunch& e, hipStream_t s) {
   const int nmb = (e.M + 127) / 128;
-  const bool vec = ((uintptr_t)e.W % 16 == 0) && (e.ldw % 2 == 0) && (e.stride_w % 2 == 0);
+  const bool vec = !e.no_vec && ((uintptr_t)e.W % 16 == 0) && (e.ldw % 2 == 0) && (e.stride_w % 2 == 0);
   // Two column tiles per wave halve the reads of H; LDS caps it at K <= 128.
   if constexpr (KT <= 4) {
     if (e.nrhs > 32) {
@@ -207,7 +207,7 @@ __global__ __launch_bounds__(256) void precoder_bf16_kernel(PrecoderLaunch e) {
   for (int mt = 0; mt < MT; ++mt) {
     const int m = mb * MB + (mt * 4 + w) * 32 + jl;
     const bool mvalid = FULL || m < e.M;
-    const float2* hcol = e.H + (int64_t)b * e.stride_h + (mvalid ? m : 0);
+    const float2* hcol = (e.H_ptrs ? e.H_ptrs[b] : e.H + (int64_t)b * e.stride_h) + (mvalid ? m : 0);
 
     floatx16 wr[NJ], wi[NJ];
 #pragma unroll
@@ -252,7 +252,7 @@ __global__ __launch_bounds__(256) void precoder_bf16_kernel(PrecoderLaunch e) {
     }
 
     if (mvalid) {
-      float2* Wb = e.W + (int64_t)b * e.stride_w + m;
+      float2* Wb = (e.W_ptrs ? e.W_ptrs[b] : e.W + (int64_t)b * e.stride_w) + m;
 #pragma unroll
       for (int t = 0; t < NJ; ++t) {
 #pragma unroll

@@ -1,0 +1,83 @@
+// Host-side policy of the request scheduler: request footprint, FIFO admission
+// under the HBM budget and grouping into batches. Plain C++ (no HIP), so it is
+// unit-tested on the host.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+namespace jacpcg {
+
+struct PendingReq {
+  uint64_t ticket;
+  size_t bytes;
+  uint64_t key;
+};
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Device workspace of one batch of G instances with K users, in launch order:
+// instance pointer arrays, A, diag(H^H H), X, per-workgroup partials and
+// statuses, per-column iterations and residuals.
+struct BatchLayout {
+  size_t hp, wp, a, gd, x, fp, wg, st, it, rr, total;
+  BatchLayout(int G, int K) {
+    const int ncb = (K + 31) / 32;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+      const size_t off = o;
+      o = align256(o + bytes);
+      return off;
+    };
+    hp = take((size_t)G * sizeof(void*));
+    wp = take((size_t)G * sizeof(void*));
+    a = take((size_t)G * K * K * 8);
+    gd = take((size_t)G * K * 4);
+    x = take((size_t)G * K * K * 8);
+    fp = take((size_t)G * ncb * 4);
+    wg = take((size_t)G * ncb * 4);
+    st = take((size_t)G * 4);
+    it = take((size_t)G * K * 4);
+    rr = take((size_t)G * K * 4);
+    total = o;
+  }
+};
+
+// Device bytes a request holds while admitted: H in, W out and its workspace.
+inline size_t request_bytes(int M, int K, int n_sub) {
+  const size_t io = (size_t)2 * n_sub * M * K * 8;
+  return io + BatchLayout(n_sub, K).total;
+}
+
+// FIFO admission under a budget (0 = unlimited): the longest prefix of `queue`
+// whose bytes fit next to `used`. Strict FIFO: a request that does not fit
+// blocks the ones behind it, so large requests cannot starve.
+inline size_t admit_prefix(const std::vector<PendingReq>& queue, size_t used, size_t budget) {
+  size_t n = 0;
+  for (const auto& q : queue) {
+    if (budget && used + q.bytes > budget) break;
+    used += q.bytes;
+    ++n;
+  }
+  return n;
+}
+
+// Admitted requests grouped by key (shape and solve settings); groups ordered
+// by their first request, requests in arrival order inside a group.
+inline std::vector<std::vector<size_t>> group_by_key(const std::vector<PendingReq>& admitted) {
+  std::vector<std::vector<size_t>> groups;
+  std::vector<uint64_t> keys;
+  for (size_t i = 0; i < admitted.size(); ++i) {
+    size_t g = 0;
+    while (g < keys.size() && keys[g] != admitted[i].key) ++g;
+    if (g == keys.size()) {
+      keys.push_back(admitted[i].key);
+      groups.emplace_back();
+    }
+    groups[g].push_back(i);
+  }
+  return groups;
+}
+
+}  // namespace jacpcg

@@ -86,6 +86,8 @@ hipError_t jacpcg_session::collect_events() {
 }
 
 void jacpcg_session::shutdown() {
+  if (sched) sched->stop();
+  sched.reset();
   (void)hipDeviceSynchronize();
   for (auto& p : pending) {
     (void)hipEventDestroy(p.a);

@@ -4,11 +4,14 @@
 
 #include <hip/hip_runtime.h>
 
+#include <chrono>
+#include <memory>
 #include <string>
 #include <vector>
 
 #include "../../include/jacpcg.h"
 #include "common.hpp"
+#include "sched.hpp"
 #include "tuner.hpp"
 
 namespace jacpcg {
@@ -38,6 +41,8 @@ struct jacpcg_session {
   jacpcg::Tuner tuner;
   bool poisoned = false;
   bool profiling = false;
+  std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+  std::unique_ptr<jacpcg::Scheduler> sched;  // created on the first request
 
   char* arena = nullptr;
   size_t arena_bytes = 0;

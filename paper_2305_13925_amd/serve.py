@@ -1,0 +1,106 @@
+"""Serving driver: a Poisson stream of precoder requests against the session's
+request API (jacpcg_submit / jacpcg_wait), reporting per-request latency
+percentiles and throughput.
+
+    python -m paper_2305_13925_amd.serve [--rate 2000] [--warmup 1] [--seconds 10]
+
+Workload (the serving workload): arrivals at `rate` requests/s with exponential
+gaps; each request draws M from {256, ..., 4096}, K from {8, ..., 256} with
+K <= M/8 and 1-64 subcarriers, xi = K/10 (10 dB), tol 1e-6 or 16 iterations.
+Channels come from a device-side pool per (M, K) shape (64 instances of the
+single-instance channel model: 4 subarrays, visibility region of 2-4, r = 0.6),
+so that generating them does not dominate the run; a request of n subcarriers
+uses the first n pool instances. Latency is t_done - t_submit of the session
+clock; throughput counts the subcarrier precoders of requests that arrived
+after the warm-up, over the time from the first such arrival to the last
+completion.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+if __package__ in (None, ""):
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+
+from paper_2305_13925_amd import binding as bd  # noqa: E402
+
+
+def run_serving(session, rate_hz=2000.0, warmup_s=1.0, measure_s=10.0, seed=0, tol=1e-6, max_iter=16,
+                precision=bd.GRAM_FP32, n_out=4, progress=None):
+    import torch
+    from channelgen import device_pool, serving_requests
+
+    reqs = serving_requests(rate_hz, warmup_s + measure_s, seed)
+    shapes = sorted({(q["M"], q["K"]) for q in reqs})
+    pools, outs = {}, {}
+    for i, (M, K) in enumerate(shapes):
+        pools[(M, K)] = device_pool(M, 4, K, 0.6, (2, 4), 64, seed * 1000 + i)
+        outs[(M, K)] = [torch.empty_like(pools[(M, K)]) for _ in range(n_out)]
+    torch.cuda.synchronize()
+    # one request per shape first, so kernel code objects are loaded before timing
+    for (M, K) in shapes:
+        t = bd.jacpcg_submit(session, pools[(M, K)][:1], outs[(M, K)][0][:1], K / 10.0, tol=tol,
+                             max_iter=max_iter, precision=precision)
+        bd.jacpcg_wait(session, t)
+    if progress:
+        progress(f"serving: {len(reqs)} requests over {len(shapes)} shapes, pools ready")
+
+    tickets = []
+    t0 = time.perf_counter()
+    for i, q in enumerate(reqs):
+        delay = t0 + q["t"] - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        key = (q["M"], q["K"])
+        n = q["n_sub"]
+        t = bd.jacpcg_submit(session, pools[key][:n], outs[key][i % n_out][:n], q["xi"], tol=tol,
+                             max_iter=max_iter, precision=precision, user_tag=i)
+        tickets.append(t)
+    results = [bd.jacpcg_wait(session, t) for t in tickets]
+    wall = time.perf_counter() - t0
+
+    meas = [(q, r) for q, r in zip(reqs, results) if q["t"] >= warmup_s]
+    lat_ms = np.array([(r["t_done_us"] - r["t_submit_us"]) / 1e3 for _, r in meas])
+    queue_ms = np.array([(r["t_admit_us"] - r["t_submit_us"]) / 1e3 for _, r in meas])
+    n_prec = sum(q["n_sub"] for q, _ in meas)
+    span_us = max(r["t_done_us"] for _, r in meas) - min(r["t_submit_us"] for _, r in meas)
+    statuses = {}
+    for _, r in meas:
+        statuses[r["status"]] = statuses.get(r["status"], 0) + 1
+    return {
+        "requests": len(meas),
+        "offered_req_per_s": rate_hz,
+        "precoders_per_s": n_prec / (span_us / 1e6),
+        "p50_ms": float(np.percentile(lat_ms, 50)),
+        "p99_ms": float(np.percentile(lat_ms, 99)),
+        "max_ms": float(lat_ms.max()),
+        "p99_queue_ms": float(np.percentile(queue_ms, 99)),
+        "statuses": {str(k): v for k, v in statuses.items()},
+        "wall_s": wall,
+        "max_iters": int(max(r["max_iters"] for _, r in meas)),
+    }
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--rate", type=float, default=2000.0)
+    ap.add_argument("--warmup", type=float, default=1.0)
+    ap.add_argument("--seconds", type=float, default=10.0)
+    ap.add_argument("--budget-gb", type=float, default=64.0)
+    ap.add_argument("--seed", type=int, default=0)
+    a = ap.parse_args(argv)
+    with bd.Session(0, hbm_budget_bytes=int(a.budget_gb * 2 ** 30)) as s:
+        out = run_serving(s, a.rate, a.warmup, a.seconds, a.seed,
+                          progress=lambda m: print(m, file=sys.stderr, flush=True))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -128,8 +128,8 @@ def test_solve_fixed_iterations(torch, sess, K, n, T, batch, identity):
     torch.cuda.synchronize()
     X = X.cpu().numpy()
     it, rr = iters.cpu().numpy(), relres.cpu().numpy()
-    # exactly T iterations, unless the FP32 residual became exactly zero (stop rule ||r|| <= 0)
-    assert np.all((it == T) | ((it < T) & (rr == 0.0)))
+    # exactly T iterations, unless the FP32 residual fell below the 2^-40 range guard
+    assert np.all((it == T) | ((it < T) & (rr <= 2.0 ** -40 * 1.01)))
     assert np.all(status.cpu().numpy() == bd.OK)
     for b in range(batch):
         Bm = None if B is None else B[b].T.astype(np.complex128)
