@@ -123,6 +123,19 @@ int jacpcg_session_set_profiling(jacpcg_session* s, int enable);
  * Synchronises the session's pending events. */
 int jacpcg_session_phase_times(jacpcg_session* s, double* ms_out, int64_t* launches_out, int reset);
 
+/* Replay identical rzf_precoder calls (same arguments and buffers, no stats,
+ * no refinement, profiling off) from a captured HIP graph: 1 = on (default),
+ * 0 = always launch kernel by kernel. */
+int jacpcg_session_set_graphs(jacpcg_session* s, int enable);
+
+/* Autotune the launch choices for one shape: times the Gram and precoder
+ * launch variants on `batch` synthetic instances of M x K (device memory from
+ * the session workspace) and keeps the fastest per (M, K, precision); the
+ * choices are saved to the session's tune cache file at destroy. Synchronises
+ * `stream`. Choices depend only on the shape, never on the batch, so results
+ * stay independent of batch composition. */
+int jacpcg_autotune(jacpcg_session* s, void* stream, int batch, int M, int K, int precision, int flags);
+
 /* ---- the three steps ---------------------------------------------------- */
 
 /* Regularised Gram (eq. 7): A_b = H_b^H H_b + xi I_K for b < batch.

@@ -109,6 +109,8 @@ def _declare(lib):
     lib.rzf_precoder_plain.argtypes = [_vp, _vp, C.c_int, C.c_int, C.c_int, _vp, _i64, _i64, C.c_double,
                                        C.c_double, C.c_double, C.c_int, C.c_int, _vp, _i64, _i64, _vp,
                                        C.POINTER(JacpcgStats)]
+    lib.jacpcg_session_set_graphs.argtypes = [_vp, C.c_int]
+    lib.jacpcg_autotune.argtypes = [_vp, _vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]
     lib.jacpcg_submit.argtypes = [_vp, C.POINTER(JacpcgRequest), C.POINTER(C.c_uint64)]
     lib.jacpcg_poll.argtypes = [_vp, C.c_uint64, C.POINTER(JacpcgResult)]
     lib.jacpcg_wait.argtypes = [_vp, C.c_uint64, C.c_int, C.POINTER(JacpcgResult)]
@@ -116,7 +118,7 @@ def _declare(lib):
     lib.jacpcg_session_clock_us.argtypes = [_vp]
     lib.jacpcg_session_clock_us.restype = C.c_double
     for name in ("jacpcg_session_create", "jacpcg_session_set_profiling", "jacpcg_session_phase_times",
-                 "jacpcg_gram", "jacpcg_solve", "rzf_precoder", "rzf_precoder_plain", "jacpcg_submit",
+                 "jacpcg_gram", "jacpcg_solve", "rzf_precoder", "rzf_precoder_plain", "jacpcg_submit", "jacpcg_session_set_graphs", "jacpcg_autotune",
                  "jacpcg_poll", "jacpcg_wait", "jacpcg_cancel"):
         getattr(lib, name).restype = C.c_int
     return lib
@@ -214,6 +216,14 @@ class Session:
 
     def set_profiling(self, enable=True):
         _check(lib().jacpcg_session_set_profiling(self.handle, int(bool(enable))))
+
+    def set_graphs(self, enable=True):
+        _check(lib().jacpcg_session_set_graphs(self.handle, int(bool(enable))))
+
+    def autotune(self, batch, M, K, precision=GRAM_FP32, flags=PRECOND_JACOBI, stream=None):
+        """jacpcg_autotune: time the launch variants of one shape and keep the fastest."""
+        _check(lib().jacpcg_autotune(self.handle, _stream(stream), int(batch), int(M), int(K), int(precision),
+                                     int(flags)))
 
     def phase_times(self, reset=False):
         ms = (C.c_double * 5)()

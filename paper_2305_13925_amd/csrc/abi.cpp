@@ -328,6 +328,26 @@ int rzf_precoder_plain(jacpcg_session* s, void* stream, int batch, int M, int K,
                           (float2*)W, ldw, stride_w, (float2*)X_out, stats);
 }
 
+int jacpcg_session_set_graphs(jacpcg_session* s, int enable) {
+  int rc = check_session(s);
+  if (rc) return rc;
+  s->use_graphs = enable != 0;
+  if (!s->use_graphs) s->graph_clear();
+  return JACPCG_OK;
+}
+
+int jacpcg_autotune(jacpcg_session* s, void* stream, int batch, int M, int K, int precision, int flags) {
+  int rc = check_gram_args(batch, M, K, (const void*)1, M, (int64_t)M * K, 1.0, nullptr, 0, 0);
+  if (rc) return rc;
+  JP_CHECK(batch >= 1, "batch must be >= 1");
+  if (precision < 0 || precision > 2) return fail(JACPCG_E_UNSUPPORTED, "unknown Gram precision %d", precision);
+  JP_CHECK((flags & ~(JACPCG_PRECOND_NONE | JACPCG_EPILOGUE_FP32)) == 0, "unknown flags 0x%x", flags);
+  rc = check_session(s);
+  if (rc) return rc;
+  JP_HIP(hipSetDevice(s->device));
+  return s->autotune((hipStream_t)stream, batch, M, K, precision, flags);
+}
+
 double jacpcg_session_clock_us(jacpcg_session* s) {
   if (!s) return 0.0;
   return std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - s->t0).count();

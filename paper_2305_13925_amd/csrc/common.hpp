@@ -88,6 +88,7 @@ struct PrecoderLaunch {
   int split;                                // 0: FP32 MFMA; 3: split-BF16 (3 parts, six products)
   const double* fpart64; int ncb64;         // nullable: FP64 ||H X||^2 partials (refined path)
   int no_vec;                               // 1: some precoder pointer or ldw does not allow 16-byte stores
+  int nj;                                   // column tiles per wave: 0 = default rule, 1 or 2 = tuned choice
 };
 
 struct Gram64Launch {
@@ -128,6 +129,7 @@ hipError_t launch_gram64(const Gram64Launch& g, hipStream_t s);
 hipError_t launch_residual(const ResidualLaunch& r, hipStream_t s);
 hipError_t launch_accumulate(const AccumulateLaunch& a, hipStream_t s);
 int residual_workgroups_per_instance(int nrhs);
+hipError_t launch_fill_synthetic(float2* H, size_t n, uint32_t seed, hipStream_t s);
 hipError_t launch_widen(const float2* X, int64_t ldx, int64_t stride_x, int batch, int K, int n,
                         double2* out, hipStream_t s);
 

@@ -124,7 +124,7 @@ hipError_t launch_kt(const PrecoderLaunch& e, hipStream_t s) {
   const bool vec = !e.no_vec && ((uintptr_t)e.W % 16 == 0) && (e.ldw % 2 == 0) && (e.stride_w % 2 == 0);
   // Two column tiles per wave halve the reads of H; LDS caps it at K <= 128.
   if constexpr (KT <= 4) {
-    if (e.nrhs > 32) {
+    if (e.nrhs > 32 && e.nj != 1) {
       const int grid = e.batch * nmb * ((e.nrhs + 63) / 64);
       if (vec)
         hipLaunchKernelGGL((precoder_f32_kernel<KT, 2, true>), dim3(grid), dim3(256), 0, s, e);
@@ -284,8 +284,11 @@ hipError_t launch_bf16_nj(const PrecoderLaunch& e, hipStream_t s) {
 
 template <int NS, int KT>
 hipError_t launch_bf16_kt(const PrecoderLaunch& e, hipStream_t s) {
-  if constexpr (KT <= 2) {
-    if (e.nrhs > 32) return launch_bf16_nj<NS, KT, 2>(e, s);
+  // Two column tiles per wave share each split of H (default up to K = 64;
+  // the tuner may choose either for K <= 128).
+  if constexpr (KT <= 4) {
+    const bool two = e.nj == 2 || (e.nj == 0 && KT <= 2);
+    if (e.nrhs > 32 && two) return launch_bf16_nj<NS, KT, 2>(e, s);
   }
   return launch_bf16_nj<NS, KT, 1>(e, s);
 }

@@ -247,7 +247,27 @@ __global__ void widen_kernel(const float2* __restrict__ X, int64_t ldx, int64_t 
   out[(int64_t)b * K * n + idx] = make_double2(v.x, v.y);
 }
 
+// Deterministic pseudo-random complex values (hash of the index), for
+// autotuning runs on synthetic data.
+__global__ void fill_synthetic_kernel(float2* __restrict__ H, size_t n, uint32_t seed) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint32_t h = (uint32_t)i * 2654435761u ^ seed;
+  h ^= h >> 15;
+  h *= 2246822519u;
+  h ^= h >> 13;
+  const float a = (float)(h & 0xffff) / 65536.0f - 0.5f;
+  const float b = (float)(h >> 16) / 65536.0f - 0.5f;
+  H[i] = make_float2(a, b);
+}
+
 }  // namespace
+
+hipError_t launch_fill_synthetic(float2* H, size_t n, uint32_t seed, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_synthetic_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, H, n, seed);
+  return hipGetLastError();
+}
 
 hipError_t launch_gram64(const Gram64Launch& g, hipStream_t s) {
   if (g.batch == 0) return hipSuccess;

@@ -28,8 +28,9 @@ int hip_error(jacpcg_session* s, hipError_t e, const char* what) {
 int jacpcg_session::reserve(const Workspace& ws) {
   if (ws.bytes <= arena_bytes) return JACPCG_OK;
   if (budget && ws.bytes > budget) return set_error(JACPCG_E_OUT_OF_MEMORY, "workspace exceeds the session budget");
-  // Work already enqueued may still use the old arena.
+  // Work already enqueued may still use the old arena; captured graphs refer to it.
   S_HIP(hipDeviceSynchronize());
+  graph_clear();
   if (arena) S_HIP(hipFree(arena));
   arena = nullptr;
   arena_bytes = 0;
@@ -85,10 +86,58 @@ hipError_t jacpcg_session::collect_events() {
   return hipSuccess;
 }
 
+uint64_t jacpcg_session::graph_key(std::initializer_list<uint64_t> fields) {
+  uint64_t h = 1469598103934665603ULL;
+  for (uint64_t v : fields) {
+    h ^= v + 0x9e3779b97f4a7c15ULL + (h << 6) + (h >> 2);
+    h *= 1099511628211ULL;
+  }
+  return h;
+}
+
+uint64_t jacpcg_session::bits_of(double d) {
+  uint64_t u;
+  std::memcpy(&u, &d, sizeof u);
+  return u;
+}
+
+hipGraphExec_t jacpcg_session::graph_lookup(uint64_t key) {
+  for (size_t i = 0; i < graphs.size(); ++i)
+    if (graphs[i].key == key) {
+      CachedGraph g = graphs[i];
+      graphs.erase(graphs.begin() + i);
+      graphs.push_back(g);
+      return g.exec;
+    }
+  return nullptr;
+}
+
+void jacpcg_session::graph_insert(uint64_t key, hipGraphExec_t exec) {
+  constexpr size_t kMaxGraphs = 32;
+  if (graphs.size() >= kMaxGraphs) {
+    (void)hipGraphExecDestroy(graphs.front().exec);
+    graphs.erase(graphs.begin());
+  }
+  graphs.push_back({key, exec});
+}
+
+void jacpcg_session::graph_clear() {
+  for (auto& g : graphs) (void)hipGraphExecDestroy(g.exec);
+  graphs.clear();
+}
+
+hipStream_t jacpcg_session::capture_stream() {
+  if (!cap_stream && hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking) != hipSuccess) cap_stream = nullptr;
+  return cap_stream;
+}
+
 void jacpcg_session::shutdown() {
   if (sched) sched->stop();
   sched.reset();
   (void)hipDeviceSynchronize();
+  graph_clear();
+  if (cap_stream) (void)hipStreamDestroy(cap_stream);
+  cap_stream = nullptr;
   for (auto& p : pending) {
     (void)hipEventDestroy(p.a);
     (void)hipEventDestroy(p.b);
@@ -144,48 +193,128 @@ int jacpcg_session::run_rzf(hipStream_t st, int batch, int M, int K, const float
   float* relres = at<float>(oR);
   float* beta = at<float>(oB);
 
-  GramLaunch g{};
-  g.H = H;
-  g.ldh = ldh;
-  g.stride_h = stride_h;
-  g.batch = batch;
-  g.M = M;
-  g.K = K;
-  g.xi = (float)xi;
-  g.A = A;
-  g.lda = K;
-  g.stride_a = (int64_t)KK;
-  g.diag = nullptr;
-  g.gdiag = gdiag;
-  g.precision = gram_prec;
-  g.m_split = tuner.gram_waves(M, K, gram_prec);
-  hipError_t e = timed(st, JACPCG_PHASE_GRAM, [&] { return launch_gram(g, st); });
-  if (e == hipErrorNotSupported) return set_error(JACPCG_E_UNSUPPORTED, "Gram precision not available");
-  if (e != hipSuccess) return hip_error(this, e, "gram launch");
+  // Gram -> persistent PCG -> status; on stream q, phases timed when `timed_run`.
+  auto enqueue_solve = [&](hipStream_t q, bool timed_run) -> hipError_t {
+    auto run = [&](int phase, auto&& launch) -> hipError_t {
+      return timed_run ? timed(q, phase, launch) : launch();
+    };
+    GramLaunch g{};
+    g.H = H;
+    g.ldh = ldh;
+    g.stride_h = stride_h;
+    g.batch = batch;
+    g.M = M;
+    g.K = K;
+    g.xi = (float)xi;
+    g.A = A;
+    g.lda = K;
+    g.stride_a = (int64_t)KK;
+    g.diag = nullptr;
+    g.gdiag = gdiag;
+    g.precision = gram_prec;
+    g.m_split = tuner.gram_waves(M, K, gram_prec);
+    hipError_t e = run(JACPCG_PHASE_GRAM, [&] { return launch_gram(g, q); });
+    if (e != hipSuccess) return e;
 
-  PcgLaunch p{};
-  p.A = A;
-  p.lda = K;
-  p.stride_a = (int64_t)KK;
-  p.B = nullptr;
-  p.X = X;
-  p.ldx = K;
-  p.stride_x = (int64_t)KK;
-  p.batch = batch;
-  p.K = K;
-  p.nrhs = K;
-  p.tol = (float)tol;
-  p.max_iter = max_iter;
-  p.precond_none = precond_none;
-  p.iters = iters;
-  p.relres = relres;
-  p.wg_status = wgs;
-  p.gdiag = gdiag;
-  p.fpart = fpart;
-  e = timed(st, JACPCG_PHASE_SOLVE, [&] { return launch_pcg(p, st, nullptr); });
-  if (e != hipSuccess) return hip_error(this, e, "pcg launch");
-  e = launch_status_reduce(wgs, ncb, batch, status, st);
-  if (e != hipSuccess) return hip_error(this, e, "status reduce launch");
+    PcgLaunch p{};
+    p.A = A;
+    p.lda = K;
+    p.stride_a = (int64_t)KK;
+    p.B = nullptr;
+    p.X = X;
+    p.ldx = K;
+    p.stride_x = (int64_t)KK;
+    p.batch = batch;
+    p.K = K;
+    p.nrhs = K;
+    p.tol = (float)tol;
+    p.max_iter = max_iter;
+    p.precond_none = precond_none;
+    p.iters = iters;
+    p.relres = relres;
+    p.wg_status = wgs;
+    p.gdiag = gdiag;
+    p.fpart = fpart;
+    e = run(JACPCG_PHASE_SOLVE, [&] { return launch_pcg(p, q, nullptr); });
+    if (e != hipSuccess) return e;
+    e = launch_status_reduce(wgs, ncb, batch, status, q);
+    if (e != hipSuccess) return e;
+    return hipSuccess;
+  };
+  // W = beta_pow H X (and the FP64 copy of X) on stream q.
+  auto enqueue_precoder = [&](hipStream_t q, bool timed_run, const double* quad64, int nq) -> hipError_t {
+    PrecoderLaunch E{};
+    E.H = H;
+    E.ldh = ldh;
+    E.stride_h = stride_h;
+    E.X = X;
+    E.ldx = K;
+    E.stride_x = (int64_t)KK;
+    E.W = W;
+    E.ldw = ldw;
+    E.stride_w = stride_w;
+    E.batch = batch;
+    E.M = M;
+    E.K = K;
+    E.nrhs = K;
+    E.fpart = fpart;
+    E.ncb = ncb;
+    E.power = (float)power;
+    E.beta_out = beta;
+    E.split = split_epilogue ? 3 : 0;
+    E.nj = tuner.precoder_nj(M, K, E.split);
+    E.fpart64 = quad64;  // refined path: ||H X64||^2 from the last FP64 residual
+    E.ncb64 = nq;
+    hipError_t e = timed_run ? timed(q, JACPCG_PHASE_EPILOGUE, [&] { return launch_precoder(E, q); })
+                             : launch_precoder(E, q);
+    if (e != hipSuccess) return e;
+    if (X64_out && !refine) e = launch_widen(X, K, (int64_t)KK, batch, K, K, X64_out, q);
+    return e;
+  };
+
+  // Repeated calls with identical arguments replay one captured HIP graph
+  // (captured on a side stream, launched on the caller's stream).
+  if (!refine && !stats && use_graphs && !profiling) {
+    const uint64_t key = graph_key({(uint64_t)batch, (uint64_t)M, (uint64_t)K, (uint64_t)(uintptr_t)H,
+                                    (uint64_t)ldh, (uint64_t)stride_h, bits_of(xi), bits_of(power), bits_of(tol),
+                                    (uint64_t)max_iter, (uint64_t)gram_prec, (uint64_t)precond_none,
+                                    (uint64_t)split_epilogue, (uint64_t)(uintptr_t)W, (uint64_t)ldw,
+                                    (uint64_t)stride_w, (uint64_t)(uintptr_t)X_out, (uint64_t)(uintptr_t)X64_out,
+                                    (uint64_t)(uintptr_t)arena});
+    hipGraphExec_t ex = graph_lookup(key);
+    if (!ex) {
+      hipStream_t cs = capture_stream();
+      hipError_t e = cs ? hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed) : hipErrorInvalidValue;
+      if (e == hipSuccess) {
+        hipError_t e1 = enqueue_solve(cs, false);
+        if (e1 == hipSuccess) e1 = enqueue_precoder(cs, false, nullptr, 0);
+        hipGraph_t graph = nullptr;
+        e = hipStreamEndCapture(cs, &graph);
+        if (e1 == hipErrorNotSupported) {
+          if (graph) (void)hipGraphDestroy(graph);
+          return set_error(JACPCG_E_UNSUPPORTED, "Gram precision not available");
+        }
+        if (e == hipSuccess && e1 == hipSuccess && graph) {
+          if (hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0) != hipSuccess) ex = nullptr;
+        }
+        if (graph) (void)hipGraphDestroy(graph);
+        if (ex) graph_insert(key, ex);
+      }
+      (void)hipGetLastError();
+    }
+    if (ex) {
+      hipError_t e = hipGraphLaunch(ex, st);
+      if (e != hipSuccess) return hip_error(this, e, "graph launch");
+      return JACPCG_OK;
+    }
+    // capture not possible: fall through to the eager launches
+  }
+
+  {
+    hipError_t e = enqueue_solve(st, true);
+    if (e == hipErrorNotSupported) return set_error(JACPCG_E_UNSUPPORTED, "Gram precision not available");
+    if (e != hipSuccess) return hip_error(this, e, "gram/pcg launch");
+  }
 
   // ---- FP64-residual iterative refinement (B = I) --------------------------
   int refine_steps = 0;
@@ -199,7 +328,7 @@ int jacpcg_session::run_rzf(hipStream_t st, int batch, int M, int K, const float
     double* scale = at<double>(oSc);
     double* rn2 = at<double>(oRn);
     Gram64Launch g64{H, ldh, stride_h, batch, M, K, xi, A64};
-    e = timed(st, JACPCG_PHASE_GRAM64, [&] { return launch_gram64(g64, st); });
+    hipError_t e = timed(st, JACPCG_PHASE_GRAM64, [&] { return launch_gram64(g64, st); });
     if (e != hipSuccess) return hip_error(this, e, "gram64 launch");
     AccumulateLaunch acc{X64, X, nullptr, batch, K, K, 1, nullptr};
     e = launch_accumulate(acc, st);  // X64 = X (exact widening)
@@ -246,36 +375,13 @@ int jacpcg_session::run_rzf(hipStream_t st, int batch, int M, int K, const float
     }
   }
 
-  PrecoderLaunch E{};
-  E.H = H;
-  E.ldh = ldh;
-  E.stride_h = stride_h;
-  E.X = X;
-  E.ldx = K;
-  E.stride_x = (int64_t)KK;
-  E.W = W;
-  E.ldw = ldw;
-  E.stride_w = stride_w;
-  E.batch = batch;
-  E.M = M;
-  E.K = K;
-  E.nrhs = K;
-  E.fpart = fpart;
-  E.ncb = ncb;
-  E.power = (float)power;
-  E.beta_out = beta;
-  E.split = split_epilogue ? 3 : 0;
-  E.fpart64 = quad;  // refined path: ||H X64||^2 from the last FP64 residual
-  E.ncb64 = n16;
-  e = timed(st, JACPCG_PHASE_EPILOGUE, [&] { return launch_precoder(E, st); });
-  if (e != hipSuccess) return hip_error(this, e, "precoder launch");
-
-  if (X64_out) {
-    if (refine)
+  {
+    hipError_t e = enqueue_precoder(st, true, quad, n16);
+    if (e != hipSuccess) return hip_error(this, e, "precoder launch");
+    if (X64_out && refine) {
       e = hipMemcpyAsync(X64_out, X64, batch * KK * sizeof(double2), hipMemcpyDeviceToDevice, st);
-    else
-      e = launch_widen(X, K, (int64_t)KK, batch, K, K, X64_out, st);
-    if (e != hipSuccess) return hip_error(this, e, "X64 output");
+      if (e != hipSuccess) return hip_error(this, e, "X64 output");
+    }
   }
 
   jacpcg_stats local_stats;
@@ -412,6 +518,7 @@ int jacpcg_session::run_rzf_plain(hipStream_t st, int batch, int M, int K, const
     E.power = (float)power;
     E.beta_out = beta + b;
     E.split = split_epilogue ? 3 : 0;
+    E.nj = tuner.precoder_nj(M, K, E.split);
     e = timed(st, JACPCG_PHASE_EPILOGUE, [&] { return launch_precoder(E, st); });
     if (e != hipSuccess) return hip_error(this, e, "precoder launch");
   }
@@ -429,4 +536,116 @@ int jacpcg_session::run_rzf_plain(hipStream_t st, int batch, int M, int K, const
   S_HIP(hipStreamSynchronize(st));
   fill_stats_host(stats, batch, K, h_it, h_rr, h_st, h_b);
   return stats->worst_status;
+}
+
+// ---------------------------------------------------------------------------
+// Autotuning: time the launch variants of one shape on synthetic data and keep
+// the fastest (Gram waves per workgroup; precoder column tiles per wave).
+// ---------------------------------------------------------------------------
+int jacpcg_session::autotune(hipStream_t st, int batch, int M, int K, int precision, int flags) {
+  const size_t KK = (size_t)K * K;
+  const int ncb = (K + 31) / 32;
+  Workspace ws;
+  const size_t oH = ws.take<float2>((size_t)batch * M * K);
+  const size_t oW = ws.take<float2>((size_t)batch * M * K);
+  const size_t oA = ws.take<float2>(batch * KK);
+  const size_t oG = ws.take<float>((size_t)batch * K);
+  const size_t oX = ws.take<float2>(batch * KK);
+  const size_t oF = ws.take<float>((size_t)batch * ncb);
+  if (int rc = reserve(ws)) return rc;
+  float2* H = at<float2>(oH);
+  float2* W = at<float2>(oW);
+  float2* A = at<float2>(oA);
+  float* gdiag = at<float>(oG);
+  float2* X = at<float2>(oX);
+  float* fpart = at<float>(oF);
+  S_HIP(launch_fill_synthetic(H, (size_t)batch * M * K, 12345u, st));
+  hipEvent_t e0 = get_event(), e1 = get_event();
+  auto time_it = [&](auto&& launch) -> float {
+    (void)launch();  // warm-up (code object load, caches)
+    (void)hipEventRecord(e0, st);
+    for (int r = 0; r < 3; ++r) (void)launch();
+    (void)hipEventRecord(e1, st);
+    (void)hipEventSynchronize(e1);
+    float ms = 1e30f;
+    if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) ms = 1e30f;
+    return ms;
+  };
+  GramLaunch g{};
+  g.H = H;
+  g.ldh = M;
+  g.stride_h = (int64_t)M * K;
+  g.batch = batch;
+  g.M = M;
+  g.K = K;
+  g.xi = 1.0f;
+  g.A = A;
+  g.lda = K;
+  g.stride_a = (int64_t)KK;
+  g.gdiag = gdiag;
+  g.precision = precision;
+  int best_w = 0;
+  float best_t = 1e30f;
+  for (int w : {2, 4, 8}) {
+    if (precision != 0 && w > 4) continue;  // split kernels take at most 4 waves
+    g.m_split = w;
+    const float t = time_it([&] { return launch_gram(g, st); });
+    if (t < best_t) {
+      best_t = t;
+      best_w = w;
+    }
+  }
+  tuner.set_gram_waves(M, K, precision, best_w);
+  g.m_split = best_w;
+  S_HIP(launch_gram(g, st));
+  PcgLaunch p{};
+  p.A = A;
+  p.lda = K;
+  p.stride_a = (int64_t)KK;
+  p.X = X;
+  p.ldx = K;
+  p.stride_x = (int64_t)KK;
+  p.batch = batch;
+  p.K = K;
+  p.nrhs = K;
+  p.max_iter = 4;
+  p.gdiag = gdiag;
+  p.fpart = fpart;
+  S_HIP(launch_pcg(p, st, nullptr));
+  PrecoderLaunch E{};
+  E.H = H;
+  E.ldh = M;
+  E.stride_h = (int64_t)M * K;
+  E.X = X;
+  E.ldx = K;
+  E.stride_x = (int64_t)KK;
+  E.W = W;
+  E.ldw = M;
+  E.stride_w = (int64_t)M * K;
+  E.batch = batch;
+  E.M = M;
+  E.K = K;
+  E.nrhs = K;
+  E.fpart = fpart;
+  E.ncb = ncb;
+  E.power = 1.0f;
+  E.split = (flags & JACPCG_EPILOGUE_FP32) ? 0 : 3;
+  int best_nj = 0;
+  best_t = 1e30f;
+  if (K <= 128 && K > 32) {
+    for (int nj : {1, 2}) {
+      E.nj = nj;
+      const float t = time_it([&] { return launch_precoder(E, st); });
+      if (t < best_t) {
+        best_t = t;
+        best_nj = nj;
+      }
+    }
+    tuner.set_precoder_nj(M, K, E.split, best_nj);
+  }
+  event_pool.push_back(e0);
+  event_pool.push_back(e1);
+  graph_clear();  // captured graphs hold the previous choices
+  S_HIP(hipStreamSynchronize(st));
+  return JACPCG_OK;
 }

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <chrono>
+#include <initializer_list>
 #include <memory>
 #include <string>
 #include <vector>
@@ -57,6 +58,23 @@ struct jacpcg_session {
   std::vector<hipEvent_t> event_pool;
   double phase_ms[JACPCG_NUM_PHASES] = {};
   int64_t phase_count[JACPCG_NUM_PHASES] = {};
+
+  // HIP graph cache of rzf_precoder launch sequences (keyed by every argument
+  // and the workspace address; cleared when the workspace moves).
+  bool use_graphs = true;
+  struct CachedGraph {
+    uint64_t key;
+    hipGraphExec_t exec;
+  };
+  std::vector<CachedGraph> graphs;  // most recent last
+  hipStream_t cap_stream = nullptr;
+  static uint64_t graph_key(std::initializer_list<uint64_t> fields);
+  static uint64_t bits_of(double d);
+  hipGraphExec_t graph_lookup(uint64_t key);
+  void graph_insert(uint64_t key, hipGraphExec_t exec);
+  void graph_clear();
+  hipStream_t capture_stream();
+  int autotune(hipStream_t st, int batch, int M, int K, int precision, int flags);
 
   // Grow the arena to hold `ws` (synchronises the device when it has to grow).
   int reserve(const jacpcg::Workspace& ws);

@@ -1,0 +1,111 @@
+"""Graph replay and autotuning: a replayed rzf_precoder graph gives the eager
+launches' result on every replay (with the inputs changed and other eager work
+in between), and the autotuned launch choices keep results within the bar."""
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2305_13925_amd import binding as bd
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "GPU tests need a HIP device"
+    return t
+
+
+def crandn(rng, *shape):
+    return ((rng.standard_normal(shape) + 1j * rng.standard_normal(shape)) / np.sqrt(2)).astype(np.complex64)
+
+
+def chan(rng, batch, K, M):
+    g = np.geomspace(1.0, 8.0, K).astype(np.float32)
+    return (crandn(rng, batch, K, M) * g[None, :, None]).astype(np.complex64)
+
+
+@pytest.mark.parametrize("M,K,batch,precision,flags", [
+    (256, 16, 8, bd.GRAM_FP32, bd.PRECOND_JACOBI),
+    (1024, 64, 16, bd.GRAM_BF16X6, bd.PRECOND_JACOBI),
+    (512, 96, 4, bd.GRAM_FP32, bd.EPILOGUE_FP32),
+    (300, 40, 5, bd.GRAM_BF16X3, bd.PRECOND_NONE),
+])
+def test_graph_replay_equals_eager(torch, M, K, batch, precision, flags):
+    rng = np.random.default_rng(M + K)
+    inputs = [chan(rng, batch, K, M) for _ in range(4)]
+    xi = K / 10.0
+    T = 8
+    with bd.Session(0) as eager, bd.Session(0) as graphed:
+        eager.set_graphs(False)
+        H = torch.empty((batch, K, M), dtype=torch.complex64, device="cuda")
+        W = torch.empty_like(H)
+        X = torch.empty((batch, K, K), dtype=torch.complex64, device="cuda")
+        other = torch.from_numpy(chan(rng, 3, 8, 64)).cuda()
+        for rep in range(6):
+            Hn = inputs[rep % len(inputs)]
+            H.copy_(torch.from_numpy(Hn))
+            bd.rzf_precoder(graphed, H, xi, max_iter=T, precision=precision, flags=flags, W=W, X_out=X)
+            W_g, X_g = W.clone(), X.clone()
+            # eager work in between: another shape on the same session, a torch op
+            bd.rzf_precoder(graphed, other, 0.8, max_iter=4)
+            _ = (H.abs() ** 2).sum()
+            torch.cuda.synchronize()
+            X_e = torch.empty_like(X)
+            W_e = bd.rzf_precoder(eager, H, xi, max_iter=T, precision=precision, flags=flags, X_out=X_e)
+            torch.cuda.synchronize()
+            assert torch.equal(W_g, W_e), f"replay {rep}: W differs from the eager launches"
+            assert torch.equal(X_g, X_e), f"replay {rep}: X differs from the eager launches"
+            if rep < 2 and precision != bd.GRAM_BF16X3:
+                ref = oracle.rzf(Hn[0].T.astype(np.complex128), xi, tol=0.0, max_iter=T,
+                                 precond="none" if flags & bd.PRECOND_NONE else "jacobi")
+                err = np.linalg.norm(W_g[0].cpu().numpy().T - ref["W"]) / np.linalg.norm(ref["W"])
+                print(f"M={M} K={K} precision={precision} replay {rep}: err vs oracle {err:.2e}")
+                assert err <= 1e-5
+
+
+def test_graph_cache_follows_workspace_growth(torch):
+    # A larger call grows (moves) the workspace; a later replay of the small
+    # shape must not use the freed workspace.
+    rng = np.random.default_rng(5)
+    small = torch.from_numpy(chan(rng, 4, 16, 128)).cuda()
+    big = torch.from_numpy(chan(rng, 64, 128, 1024)).cuda()
+    with bd.Session(0) as s, bd.Session(0) as e:
+        e.set_graphs(False)
+        W0 = bd.rzf_precoder(s, small, 1.6, max_iter=8)
+        Wb = bd.rzf_precoder(s, big, 12.8, max_iter=8)
+        W1 = bd.rzf_precoder(s, small, 1.6, max_iter=8)
+        W1b = bd.rzf_precoder(s, small, 1.6, max_iter=8, W=torch.empty_like(small))
+        torch.cuda.synchronize()
+        assert torch.equal(W0, W1) and torch.equal(W0, W1b)
+        assert torch.equal(Wb, bd.rzf_precoder(e, big, 12.8, max_iter=8))
+
+
+@pytest.mark.parametrize("M,K,precision,flags", [
+    (1024, 64, bd.GRAM_BF16X6, bd.PRECOND_JACOBI),
+    (2048, 128, bd.GRAM_FP32, bd.PRECOND_JACOBI),
+    (512, 48, bd.GRAM_FP32, bd.EPILOGUE_FP32),
+])
+def test_autotune_keeps_results_within_bar(torch, tmp_path, M, K, precision, flags):
+    rng = np.random.default_rng(K)
+    Hn = chan(rng, 6, K, M)
+    H = torch.from_numpy(Hn).cuda()
+    xi = K / 10.0
+    cache = tmp_path / "tune.json"
+    with bd.Session(0, tune_cache_path=str(cache)) as s:
+        s.autotune(64, M, K, precision, flags)
+        W, st, _ = bd.rzf_precoder(s, H, xi, max_iter=8, precision=precision, flags=flags, stats=True)
+        torch.cuda.synchronize()
+    text = cache.read_text()
+    assert '"gram_waves"' in text and f"[{M}, {K}, {precision}," in text
+    for b in (0, 5):
+        ref = oracle.rzf(Hn[b].T.astype(np.complex128), xi, tol=0.0, max_iter=8)
+        got = W[b].cpu().numpy().T
+        assert np.linalg.norm(got - ref["W"]) / np.linalg.norm(ref["W"]) <= 1e-5
+    # a new session reads the cache and computes the same result
+    with bd.Session(0, tune_cache_path=str(cache)) as s2:
+        W2 = bd.rzf_precoder(s2, H, xi, max_iter=8, precision=precision, flags=flags)
+        torch.cuda.synchronize()
+    assert torch.equal(W, W2)
