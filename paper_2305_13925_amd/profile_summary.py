@@ -1,0 +1,158 @@
+"""Summaries of rocprofv3 output for the precoder's kernels.
+
+    python -m paper_2305_13925_amd.profile_summary trace <kernel_trace.csv> --title T --cmd C
+        markdown table of per-kernel dispatch durations (grouped by kernel and grid)
+
+    python -m paper_2305_13925_amd.profile_summary traffic --fetch D --write D \
+            --copy-fetch D --copy-write D --copy-bytes N --cmd C --out profiles/hbm_traffic
+        HBM bytes per dispatch of the Gram, PCG and precoder kernels from a
+        FETCH_SIZE pass and a WRITE_SIZE pass (each a rocprofv3 --pmc output
+        directory), each scaled by what the same counter reads for a plain copy
+        kernel of N bytes read and N bytes written. Writes <out>.json (read by
+        bench.py; tied to the sha256 of the kernel sources) and <out>.md.
+"""
+
+from __future__ import annotations
+
+import argparse
+import collections
+import csv
+import glob
+import hashlib
+import json
+import os
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+KERNEL_SOURCES = ["paper_2305_13925_amd/csrc/gram.hip", "paper_2305_13925_amd/csrc/pcg.hip",
+                  "paper_2305_13925_amd/csrc/precoder.hip", "paper_2305_13925_amd/csrc/device_util.hpp",
+                  "paper_2305_13925_amd/csrc/common.hpp"]
+PHASE_PREFIX = {"gram": "gram_", "solve": "pcg_", "epilogue": "precoder_"}
+
+
+def short_name(name):
+    return name.replace("jacpcg::(anonymous namespace)::", "").replace("void ", "")
+
+
+def grid_of(r):
+    return int(r.get("Grid_Size_X") or r.get("Grid_Size") or 0)
+
+
+def trace_table(path, title, cmd):
+    rows = list(csv.DictReader(open(path)))
+    d = collections.defaultdict(list)
+    for r in rows:
+        key = (r["Kernel_Name"], grid_of(r), int(r.get("Workgroup_Size_X") or r.get("Workgroup_Size") or 0),
+               r.get("VGPR_Count"), r.get("Accum_VGPR_Count"), r.get("LDS_Block_Size"))
+        d[key].append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    out = [f"# {title}\n", "Command (run from the repository root on one MI355X):\n", "```", cmd, "```\n",
+           "Per-dispatch durations from the kernel trace, grouped by kernel and grid size (threads).\n",
+           "| kernel | grid (threads) | WG | VGPR | AGPR | LDS B | dispatches | avg us | min us | max us |",
+           "|---|---|---|---|---|---|---|---|---|---|"]
+    for k, v in sorted(d.items(), key=lambda kv: -sum(kv[1])):
+        name = short_name(k[0])
+        if len(name) > 70:
+            name = name[:70] + "..."
+        out.append(f"| `{name}` | {k[1]} | {k[2]} | {k[3]} | {k[4]} | {k[5]} | {len(v)} | "
+                   f"{sum(v) / len(v) / 1e3:.2f} | {min(v) / 1e3:.2f} | {max(v) / 1e3:.2f} |")
+    return "\n".join(out) + "\n"
+
+
+def counter_rows(d):
+    files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise FileNotFoundError(f"no counter_collection.csv under {d}")
+    return list(csv.DictReader(open(files[0])))
+
+
+def per_dispatch(rows, counter):
+    """{(kernel, grid): [value per dispatch]} of one counter (summed over its instances)."""
+    acc = collections.defaultdict(float)
+    meta = {}
+    for r in rows:
+        if r["Counter_Name"] != counter:
+            continue
+        did = r.get("Dispatch_Id") or r.get("Correlation_Id")
+        acc[did] += float(r["Counter_Value"])
+        meta[did] = (r["Kernel_Name"], grid_of(r))
+    out = collections.defaultdict(list)
+    for did, v in acc.items():
+        out[meta[did]].append(v)
+    return out
+
+
+def largest(per, prefix):
+    """Dispatches of the largest-grid launch of the kernel whose short name starts with prefix."""
+    cands = [(k, v) for k, v in per.items() if short_name(k[0]).startswith(prefix)]
+    if not cands:
+        return None, []
+    k, v = max(cands, key=lambda kv: (kv[0][1], len(kv[1])))
+    return k, v
+
+
+def traffic(a):
+    kib = 1024.0
+    cf = per_dispatch(counter_rows(a.copy_fetch), "FETCH_SIZE")
+    cw = per_dispatch(counter_rows(a.copy_write), "WRITE_SIZE")
+    copy_f = max((max(v) for v in cf.values()), default=0.0) * kib
+    copy_w = max((max(v) for v in cw.values()), default=0.0) * kib
+    f_scale = a.copy_bytes / copy_f
+    w_scale = a.copy_bytes / copy_w
+    fetch = per_dispatch(counter_rows(a.fetch), "FETCH_SIZE")
+    write = per_dispatch(counter_rows(a.write), "WRITE_SIZE")
+    rec = {"per_launch_bytes": {}, "fetch_bytes": {}, "write_bytes": {}, "kernels": {},
+           "calibration": {"copy_bytes": a.copy_bytes, "fetch_counter_bytes": copy_f, "write_counter_bytes": copy_w,
+                           "fetch_scale": f_scale, "write_scale": w_scale},
+           "command": a.cmd,
+           "sources": {f: hashlib.sha256(open(os.path.join(ROOT, f), "rb").read()).hexdigest()
+                       for f in KERNEL_SOURCES}}
+    lines = ["# HBM traffic per launch (rocprofv3 FETCH_SIZE / WRITE_SIZE)\n",
+             "Commands (run from the repository root on one MI355X; one counter per pass):\n", "```", a.cmd, "```\n",
+             f"Calibration: a plain copy of {a.copy_bytes / 2**30:.2f} GiB reads FETCH_SIZE = "
+             f"{copy_f / 2**30:.3f} GiB and WRITE_SIZE = {copy_w / 2**30:.3f} GiB, so fetch counts are "
+             f"scaled by {f_scale:.3f} and write counts by {w_scale:.3f}.\n",
+             "| phase | kernel | grid | dispatches | fetch MB (scaled) | write MB (scaled) | total MB |",
+             "|---|---|---|---|---|---|---|"]
+    for phase, prefix in PHASE_PREFIX.items():
+        kf, vf = largest(fetch, prefix)
+        kw, vw = largest(write, prefix)
+        if not vf or not vw:
+            continue
+        fb = sum(vf) / len(vf) * kib * f_scale
+        wb = sum(vw) / len(vw) * kib * w_scale
+        rec["per_launch_bytes"][phase] = fb + wb
+        rec["fetch_bytes"][phase] = fb
+        rec["write_bytes"][phase] = wb
+        rec["kernels"][phase] = short_name(kf[0])
+        lines.append(f"| {phase} | `{short_name(kf[0])[:60]}` | {kf[1]} | {len(vf)} | {fb / 1e6:.1f} | "
+                     f"{wb / 1e6:.1f} | {(fb + wb) / 1e6:.1f} |")
+    json.dump(rec, open(a.out + ".json", "w"), indent=1)
+    open(a.out + ".md", "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd_name", required=True)
+    t = sub.add_parser("trace")
+    t.add_argument("csv")
+    t.add_argument("--title", required=True)
+    t.add_argument("--cmd", required=True)
+    t.add_argument("--out")
+    f = sub.add_parser("traffic")
+    for n in ("fetch", "write", "copy_fetch", "copy_write"):
+        f.add_argument("--" + n.replace("_", "-"), dest=n, required=True)
+    f.add_argument("--copy-bytes", type=float, required=True)
+    f.add_argument("--cmd", required=True)
+    f.add_argument("--out", required=True)
+    a = ap.parse_args(argv)
+    if a.cmd_name == "trace":
+        text = trace_table(a.csv, a.title, a.cmd)
+        if a.out:
+            open(a.out, "w").write(text)
+        print(text)
+    else:
+        traffic(a)
+
+
+if __name__ == "__main__":
+    main()
