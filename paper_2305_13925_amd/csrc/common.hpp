@@ -89,6 +89,7 @@ struct PrecoderLaunch {
   const double* fpart64; int ncb64;         // nullable: FP64 ||H X||^2 partials (refined path)
   int no_vec;                               // 1: some precoder pointer or ldw does not allow 16-byte stores
   int nj;                                   // column tiles per wave: 0 = default rule, 1 or 2 = tuned choice
+  int mtiles;                               // split-BF16: 128-antenna blocks per workgroup (0 = default rule)
 };
 
 struct Gram64Launch {

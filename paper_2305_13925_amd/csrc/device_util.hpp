@@ -14,6 +14,36 @@ __device__ __forceinline__ int xcd_remap(int g, int n) {
   return (g & 7) * (n >> 3) + (g >> 3);
 }
 
+// Global-memory (address space 1) view of a generic pointer. Accesses through
+// it compile to global_* instructions, which only the vector-memory counter
+// tracks. Through a generic pointer (one selected from a pointer array or a
+// base + offset) they become flat_* instructions, which the LDS counter tracks
+// as well, so every LDS read would also wait for all loads still in flight.
+template <class T>
+using gptr = __attribute__((address_space(1))) T*;
+template <class T>
+__device__ __forceinline__ gptr<T> as_global(T* p) {
+  return (gptr<T>)p;
+}
+
+typedef float gfloat2 __attribute__((ext_vector_type(2)));
+// Complex entry p[0] through a global pointer (one 8-byte load).
+__device__ __forceinline__ float2 ld2(gptr<const float2> p) {
+  const gfloat2 v = *reinterpret_cast<gptr<const gfloat2>>(p);
+  return make_float2(v.x, v.y);
+}
+typedef float gfloat4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float4 ld4(gptr<const float4> p) {
+  const gfloat4 v = *reinterpret_cast<gptr<const gfloat4>>(p);
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void st4(gptr<float4> p, float a, float b, float c, float d) {
+  *reinterpret_cast<gptr<gfloat4>>(p) = gfloat4{a, b, c, d};
+}
+__device__ __forceinline__ void st2(gptr<float2> p, float re, float im) {
+  *reinterpret_cast<gptr<gfloat2>>(p) = gfloat2{re, im};
+}
+
 __device__ __forceinline__ floatx16 mfma32(float a, float b, floatx16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
 }

@@ -31,19 +31,18 @@ __device__ __forceinline__ void upper_tile(int t, int nt, int& ti, int& tj) {
 // Load 8 consecutive complex entries row[m .. m+7], zero past `mend` or when the
 // row is padding. VEC: 16-byte aligned row and m multiple of 8.
 template <bool VEC>
-__device__ __forceinline__ void load8(const float2* __restrict__ row, int m, int mend, bool valid,
-                                      float2 (&v)[8]) {
+__device__ __forceinline__ void load8(gptr<const float2> row, int m, int mend, bool valid, float2 (&v)[8]) {
   if (VEC && valid && m + 8 <= mend) {
-    const float4* p = reinterpret_cast<const float4*>(row + m);
+    gptr<const float4> p = reinterpret_cast<gptr<const float4>>(row + m);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const float4 t = p[q];
+      const float4 t = ld4(p + q);
       v[2 * q] = make_float2(t.x, t.y);
       v[2 * q + 1] = make_float2(t.z, t.w);
     }
   } else {
 #pragma unroll
-    for (int e = 0; e < 8; ++e) v[e] = (valid && m + e < mend) ? row[m + e] : make_float2(0.f, 0.f);
+    for (int e = 0; e < 8; ++e) v[e] = (valid && m + e < mend) ? ld2(row + m + e) : make_float2(0.f, 0.f);
   }
 }
 
@@ -69,16 +68,16 @@ __device__ __forceinline__ void panel_tiles(int p, int nt, int& ti, int& tj0, in
 // 4 consecutive complex entries row[m .. m+3] as 8 floats (re, im, ...), zero
 // past `mend` or for a padding row.
 template <bool VEC>
-__device__ __forceinline__ void load4c(const float2* __restrict__ row, int m, int mend, bool valid, float (&v)[8]) {
+__device__ __forceinline__ void load4c(gptr<const float2> row, int m, int mend, bool valid, float (&v)[8]) {
   if (VEC && valid && m + 4 <= mend) {
-    const float4* p = reinterpret_cast<const float4*>(row + m);
-    const float4 a = p[0], c = p[1];
+    gptr<const float4> p = reinterpret_cast<gptr<const float4>>(row + m);
+    const float4 a = ld4(p), c = ld4(p + 1);
     v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
     v[4] = c.x; v[5] = c.y; v[6] = c.z; v[7] = c.w;
   } else {
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      const float2 t = (valid && m + e < mend) ? row[m + e] : make_float2(0.f, 0.f);
+      const float2 t = (valid && m + e < mend) ? ld2(row + m + e) : make_float2(0.f, 0.f);
       v[2 * e] = t.x;
       v[2 * e + 1] = t.y;
     }
@@ -152,11 +151,11 @@ __global__ __launch_bounds__(512) void gram_f32_kernel(GramLaunch g) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nw = blockDim.x >> 6;
   const int half = lane >> 5, li = lane & 31;
-  const float2* Hb = g.H_ptrs ? g.H_ptrs[b] : g.H + (int64_t)b * g.stride_h;
+  gptr<const float2> Hb = as_global(g.H_ptrs ? g.H_ptrs[b] : g.H + (int64_t)b * g.stride_h);
   const int ui = ti * 32 + li, uj = tj * 32 + li;
   const bool vi = ui < g.K, vj = uj < g.K;
-  const float2* hi = Hb + (int64_t)(vi ? ui : 0) * g.ldh;
-  const float2* hj = Hb + (int64_t)(vj ? uj : 0) * g.ldh;
+  gptr<const float2> hi = Hb + (int64_t)(vi ? ui : 0) * g.ldh;
+  gptr<const float2> hj = Hb + (int64_t)(vj ? uj : 0) * g.ldh;
   const bool same = (ti == tj);
 
   const int chunk = ((g.M + nw * 8 - 1) / (nw * 8)) * 8;
@@ -206,17 +205,17 @@ __global__ __launch_bounds__(256) void gram_bf16_kernel(GramLaunch g) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nw = blockDim.x >> 6;
   const int half = lane >> 5, li = lane & 31;
-  const float2* Hb = g.H_ptrs ? g.H_ptrs[b] : g.H + (int64_t)b * g.stride_h;
+  gptr<const float2> Hb = as_global(g.H_ptrs ? g.H_ptrs[b] : g.H + (int64_t)b * g.stride_h);
   const int ui = ti * 32 + li;
   const bool vi = ui < g.K;
-  const float2* hi = Hb + (int64_t)(vi ? ui : 0) * g.ldh;
+  gptr<const float2> hi = Hb + (int64_t)(vi ? ui : 0) * g.ldh;
   // Tile t of the panel is (ti, tj0 + t). The diagonal tile reuses the row
   // block; every other tile has its own column block of users, loaded and split.
   const bool diag0 = (tj0 == ti);
   const int nx = ntj - (diag0 ? 1 : 0);  // 0, 1 or 2 column blocks to load
   const int xoff = diag0 ? 1 : 0;        // tile index of column block q is q + xoff
   bool vx[2];
-  const float2* hx[2];
+  gptr<const float2> hx[2];
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
     const int ux = (tj0 + q + xoff) * 32 + li;
@@ -234,13 +233,13 @@ __global__ __launch_bounds__(256) void gram_bf16_kernel(GramLaunch g) {
     accR[t] = zero16();
     accI[t] = zero16();
   }
-  auto load = [&](const float2* row, bool valid, int m, float (&re)[8], float (&im)[8]) {
+  auto load = [&](gptr<const float2> row, bool valid, int m, float (&re)[8], float (&im)[8]) {
     const int mm = m + 8 * half;
     if (VEC && valid && mm + 8 <= m1) {
-      const float4* p = reinterpret_cast<const float4*>(row + mm);
+      gptr<const float4> p = reinterpret_cast<gptr<const float4>>(row + mm);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const float4 t = p[q];
+        const float4 t = ld4(p + q);
         re[2 * q] = t.x;
         im[2 * q] = t.y;
         re[2 * q + 1] = t.z;
@@ -249,7 +248,7 @@ __global__ __launch_bounds__(256) void gram_bf16_kernel(GramLaunch g) {
     } else {
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
-        const float2 t = (valid && mm + e < m1) ? row[mm + e] : make_float2(0.f, 0.f);
+        const float2 t = (valid && mm + e < m1) ? ld2(row + mm + e) : make_float2(0.f, 0.f);
         re[e] = t.x;
         im[e] = t.y;
       }
@@ -299,30 +298,34 @@ __global__ __launch_bounds__(256) void gram_bf16_kernel(GramLaunch g) {
 }
 
 
-// Split-BF16 Gram for K <= 64: one workgroup per instance; each wave takes a
-// contiguous quarter of the antennas, splits each of the (at most two) user
-// blocks once per 16 antennas and forms all upper tiles (0,0), (0,1), (1,1)
-// from those splits, so the split work per MFMA is a third of the panel
-// kernel's. The next step's channel values are loaded before the products.
-template <int NS, int NT>
+// Split-BF16 Gram for K <= 64: one workgroup per instance; each wave takes
+// every nw-th 16-antenna step, splits each of the (at most two) user blocks
+// once per step and forms all upper tiles (0,0), (0,1), (1,1) from those
+// splits, so the split work per MFMA is a third of the panel kernel's. The
+// next step's channel values are loaded before the products.
+// EXACT: M is a multiple of 16 and the rows are 16-byte aligned, so every
+// lane's 8 antennas are in range and the loads need no per-lane branch (rows
+// past K repeat user 0; they feed only entries of A that are never written).
+template <int NS, int NT, bool EXACT>
 __global__ __launch_bounds__(256) void gram_bf16_small_kernel(GramLaunch g) {
   constexpr int NTILE = NT * (NT + 1) / 2;
   const int b = xcd_remap(blockIdx.x, gridDim.x);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
   const int nw = blockDim.x >> 6;
   const int half = lane >> 5, li = lane & 31;
-  const float2* Hb = g.H_ptrs ? g.H_ptrs[b] : g.H + (int64_t)b * g.stride_h;
+  gptr<const float2> Hb = as_global(g.H_ptrs ? g.H_ptrs[b] : g.H + (int64_t)b * g.stride_h);
   bool vu[NT];
-  const float2* row[NT];
+  gptr<const float2> row[NT];
 #pragma unroll
   for (int q = 0; q < NT; ++q) {
     const int u = q * 32 + li;
     vu[q] = u < g.K;
     row[q] = Hb + (int64_t)(vu[q] ? u : 0) * g.ldh;
   }
-  const int chunk = ((g.M + nw * 16 - 1) / (nw * 16)) * 16;
-  const int m0 = wave * chunk;
-  const int m1 = min(g.M, m0 + chunk);
+  const int mstep = nw * 16;
+  const int m0 = wave * 16;
+  const int m1 = g.M;
   const bool vec = !g.no_vec && ((uintptr_t)g.H % 16 == 0) && (g.ldh % 2 == 0) && (g.stride_h % 2 == 0);
 
   floatx16 accR[NTILE], accI[NTILE];
@@ -333,11 +336,11 @@ __global__ __launch_bounds__(256) void gram_bf16_small_kernel(GramLaunch g) {
   }
   auto load = [&](int q, int m, float (&re)[8], float (&im)[8]) {
     const int mm = m + 8 * half;
-    if (vec && vu[q] && mm + 8 <= m1) {
-      const float4* p = reinterpret_cast<const float4*>(row[q] + mm);
+    if (EXACT || (vec && vu[q] && mm + 8 <= m1)) {
+      gptr<const float4> p = reinterpret_cast<gptr<const float4>>(row[q] + mm);
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
-        const float4 t = p[c];
+        const float4 t = ld4(p + c);
         re[2 * c] = t.x;
         im[2 * c] = t.y;
         re[2 * c + 1] = t.z;
@@ -346,28 +349,27 @@ __global__ __launch_bounds__(256) void gram_bf16_small_kernel(GramLaunch g) {
     } else {
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
-        const float2 t = (vu[q] && mm + e < m1) ? row[q][mm + e] : make_float2(0.f, 0.f);
+        const float2 t = (vu[q] && mm + e < m1) ? ld2(row[q] + mm + e) : make_float2(0.f, 0.f);
         re[e] = t.x;
         im[e] = t.y;
       }
     }
   };
-  float re[NT][8], im[NT][8];
-  if (m0 < m1) {
-#pragma unroll
-    for (int q = 0; q < NT; ++q) load(q, m0, re[q], im[q]);
-  }
-  for (int m = m0; m < m1; m += 16) {
+  // One 16-antenna step from staged values: split, refill the stage with the
+  // step `ahead` steps later (unconditionally: past the end it reloads the
+  // current step, so no join has to wait for the load), then the products of
+  // every upper tile.
+  auto step = [&](float (&re)[NT][8], float (&im)[NT][8], int m, int ahead) {
     u32x4 Pr[NT][NS], Pi[NT][NS];
 #pragma unroll
     for (int q = 0; q < NT; ++q) {
       split8<NS>(re[q], Pr[q]);
       split8<NS>(im[q], Pi[q]);
     }
-    if (m + 16 < m1) {
+    const int mnext = (m + ahead * mstep < m1) ? m + ahead * mstep : m;
 #pragma unroll
-      for (int q = 0; q < NT; ++q) load(q, m + 16, re[q], im[q]);
-    }
+    for (int q = 0; q < NT; ++q) load(q, mnext, re[q], im[q]);
+    __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the products
     int t = 0;
 #pragma unroll
     for (int a = 0; a < NT; ++a) {
@@ -384,6 +386,26 @@ __global__ __launch_bounds__(256) void gram_bf16_small_kernel(GramLaunch g) {
         split_mma<NS>(An, Pr[c], accI[t]);
       }
     }
+  };
+  if constexpr (EXACT) {
+    // M is a multiple of 2 * mstep: two stages, each refilled two steps ahead.
+    float reA[NT][8], imA[NT][8], reB[NT][8], imB[NT][8];
+#pragma unroll
+    for (int q = 0; q < NT; ++q) {
+      load(q, m0, reA[q], imA[q]);
+      load(q, m0 + mstep, reB[q], imB[q]);
+    }
+    for (int m = m0; m < m1; m += 2 * mstep) {
+      step(reA, imA, m, 2);
+      step(reB, imB, m + mstep, 2);
+    }
+  } else {
+    float re[NT][8], im[NT][8];
+    if (m0 < m1) {
+#pragma unroll
+      for (int q = 0; q < NT; ++q) load(q, m0, re[q], im[q]);
+    }
+    for (int m = m0; m < m1; m += mstep) step(re, im, m, 1);
   }
 
   extern __shared__ float red_dyn[];
@@ -421,16 +443,23 @@ hipError_t launch_gram(const GramLaunch& g, hipStream_t s) {
     const size_t lds = (size_t)wb * 2 * 16 * 64 * sizeof(float);
     if (nt <= 2) {
       const dim3 grid1((unsigned)g.batch);
+      const bool exact = vec && (g.M % (32 * wb) == 0);
+      auto pick = [&](auto k_exact, auto k_any) {
+        if (exact)
+          hipLaunchKernelGGL(k_exact, grid1, block, lds, s, g);
+        else
+          hipLaunchKernelGGL(k_any, grid1, block, lds, s, g);
+      };
       if (g.precision == 1) {
         if (nt == 1)
-          hipLaunchKernelGGL((gram_bf16_small_kernel<2, 1>), grid1, block, lds, s, g);
+          pick(gram_bf16_small_kernel<2, 1, true>, gram_bf16_small_kernel<2, 1, false>);
         else
-          hipLaunchKernelGGL((gram_bf16_small_kernel<2, 2>), grid1, block, lds, s, g);
+          pick(gram_bf16_small_kernel<2, 2, true>, gram_bf16_small_kernel<2, 2, false>);
       } else {
         if (nt == 1)
-          hipLaunchKernelGGL((gram_bf16_small_kernel<3, 1>), grid1, block, lds, s, g);
+          pick(gram_bf16_small_kernel<3, 1, true>, gram_bf16_small_kernel<3, 1, false>);
         else
-          hipLaunchKernelGGL((gram_bf16_small_kernel<3, 2>), grid1, block, lds, s, g);
+          pick(gram_bf16_small_kernel<3, 2, true>, gram_bf16_small_kernel<3, 2, false>);
       }
       return hipGetLastError();
     }

@@ -94,8 +94,10 @@ __device__ __forceinline__ void apply_a(floatx16& qr, floatx16& qi, const float*
   }
 }
 
+// Two waves per SIMD (the register budget of 256 per lane) let one workgroup's
+// reductions overlap another's products.
 template <int KT, bool AREG>
-__global__ __launch_bounds__(KT * 64) void pcg_f32_kernel(PcgLaunch p) {
+__global__ __launch_bounds__(KT * 64) __attribute__((amdgpu_waves_per_eu(2))) void pcg_f32_kernel(PcgLaunch p) {
   constexpr int KP = KT * 32;
   constexpr int KH = KT * 16;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;

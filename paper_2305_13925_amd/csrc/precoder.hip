@@ -11,6 +11,8 @@
 // beta_pow * X for the block's columns is staged in LDS once. On
 // v_mfma_f32_32x32x2_f32 the two k slots carry users k = s and k = s + K/2, so
 // each lane half reads one user's antenna column of H, coalesced along m.
+#include <algorithm>
+
 #include "device_util.hpp"
 
 namespace jacpcg {
@@ -34,7 +36,7 @@ __global__ __launch_bounds__(256) void precoder_f32_kernel(PrecoderLaunch e) {
   constexpr int KP = KT * 32;
   constexpr int KH = KT * 16;
   constexpr int NC = 32 * NJ;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int jl = lane & 31, half = lane >> 5;
   const int nmb = (e.M + 127) / 128;
   const int ncw = (e.nrhs + NC - 1) / NC;
@@ -50,13 +52,13 @@ __global__ __launch_bounds__(256) void precoder_f32_kernel(PrecoderLaunch e) {
   const float beta = power_factor(e, b);
   if (e.beta_out && mb == 0 && cw == 0 && threadIdx.x == 0) e.beta_out[b] = beta;
 
-  const float2* Xb = e.X + (int64_t)b * e.stride_x;
+  gptr<const float2> Xb = as_global(e.X + (int64_t)b * e.stride_x);
   for (int idx = threadIdx.x; idx < KP * NC; idx += 256) {
     const int jj = idx % NC, k = idx / NC;
     const int j = cw * NC + jj;
     float2 v = make_float2(0.f, 0.f);
     if (k < K && j < e.nrhs) {
-      v = Xb[(int64_t)j * e.ldx + k];
+      v = ld2(Xb + (int64_t)j * e.ldx + k);
       v.x *= beta;
       v.y *= beta;
     }
@@ -68,7 +70,8 @@ __global__ __launch_bounds__(256) void precoder_f32_kernel(PrecoderLaunch e) {
   const int mrow = m0 + jl;
   const bool mvalid = mrow < e.M;
   const int klim = max(0, min(KH, K - half * KH));
-  const float2* hcol = (e.H_ptrs ? e.H_ptrs[b] : e.H + (int64_t)b * e.stride_h) + (int64_t)(half * KH) * e.ldh + (mvalid ? mrow : 0);
+  gptr<const float2> hcol = as_global(e.H_ptrs ? e.H_ptrs[b] : e.H + (int64_t)b * e.stride_h) + (int64_t)(half * KH) * e.ldh +
+                           (mvalid ? mrow : 0);
 
   floatx16 wr[NJ], wi[NJ];
 #pragma unroll
@@ -81,7 +84,7 @@ __global__ __launch_bounds__(256) void precoder_f32_kernel(PrecoderLaunch e) {
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int s = s0 + q;
-      h[q] = (mvalid && s < klim) ? hcol[(int64_t)s * e.ldh] : make_float2(0.f, 0.f);
+      h[q] = (mvalid && s < klim) ? ld2(hcol + (int64_t)s * e.ldh) : make_float2(0.f, 0.f);
     }
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
@@ -96,23 +99,23 @@ __global__ __launch_bounds__(256) void precoder_f32_kernel(PrecoderLaunch e) {
     }
   }
 
-  float2* Wb = (e.W_ptrs ? e.W_ptrs[b] : e.W + (int64_t)b * e.stride_w);
+  gptr<float2> Wb = as_global(e.W_ptrs ? e.W_ptrs[b] : e.W + (int64_t)b * e.stride_w);
 #pragma unroll
   for (int t = 0; t < NJ; ++t) {
     const int j = cw * NC + t * 32 + jl;
     if (j >= e.nrhs) continue;
-    float2* wc = Wb + (int64_t)j * e.ldw;
+    gptr<float2> wc = Wb + (int64_t)j * e.ldw;
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
       const int m = m0 + 8 * g + 4 * half;
       if (VEC && m + 4 <= e.M) {
-        float4* dst = reinterpret_cast<float4*>(wc + m);
-        dst[0] = make_float4(wr[t][4 * g + 0], wi[t][4 * g + 0], wr[t][4 * g + 1], wi[t][4 * g + 1]);
-        dst[1] = make_float4(wr[t][4 * g + 2], wi[t][4 * g + 2], wr[t][4 * g + 3], wi[t][4 * g + 3]);
+        gptr<float4> dst = reinterpret_cast<gptr<float4>>(wc + m);
+        st4(dst, wr[t][4 * g + 0], wi[t][4 * g + 0], wr[t][4 * g + 1], wi[t][4 * g + 1]);
+        st4(dst + 1, wr[t][4 * g + 2], wi[t][4 * g + 2], wr[t][4 * g + 3], wi[t][4 * g + 3]);
       } else {
 #pragma unroll
         for (int q = 0; q < 4; ++q)
-          if (m + q < e.M) wc[m + q] = make_float2(wr[t][4 * g + q], wi[t][4 * g + q]);
+          if (m + q < e.M) st2(wc + m + q, wr[t][4 * g + q], wi[t][4 * g + q]);
       }
     }
   }
@@ -154,21 +157,25 @@ hipError_t launch_kt(const PrecoderLaunch& e, hipStream_t s) {
 // beta_pow X is split into bf16 parts once per workgroup (Re and Im planes in
 // LDS); H is split on the fly and its negated Im plane is shared by all column
 // tiles, so no other operand shuffling is needed.
-template <int NS, int KT, int NJ, int MT, bool FULL>
+template <int NS, int KT, int NJ, bool FULL>
 __global__ __launch_bounds__(256) void precoder_bf16_kernel(PrecoderLaunch e) {
   constexpr int KP = KT * 32;
   constexpr int K8 = KP / 8;  // groups of 8 users (one lane half of one step)
   constexpr int NC = 32 * NJ;
-  constexpr int MB = 128 * MT;  // antennas per workgroup: MT tiles of 32 per wave
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int jl = lane & 31, half = lane >> 5;
-  const int nmb = (e.M + MB - 1) / MB;
+  // A workgroup covers `mt` consecutive blocks of 128 antennas (one 32-antenna
+  // tile per wave and block), so its split of beta_pow X is reused mt times.
+  const int mt = e.mtiles;
+  const int nblk = (e.M + 127) / 128;
+  const int nmb = (nblk + mt - 1) / mt;
   const int ncw = (e.nrhs + NC - 1) / NC;
   const int per = nmb * ncw;
   const int L = xcd_remap(blockIdx.x, gridDim.x);
   const int b = L / per;
   const int rem = L - b * per;
   const int mb = rem / ncw, cw = rem - mb * ncw;
+  const int blk0 = mb * mt, blk1 = min(nblk, blk0 + mt);
   const int K = e.K;
 
   extern __shared__ u32x4 xs_dyn[];  // [2 planes][NS][K8][NC]
@@ -176,10 +183,39 @@ __global__ __launch_bounds__(256) void precoder_bf16_kernel(PrecoderLaunch e) {
     return xs_dyn[(((size_t)plane * NS + s) * K8 + k8) * NC + j];
   };
 
+  gptr<const float2> Hb = as_global(e.H_ptrs ? e.H_ptrs[b] : e.H + (int64_t)b * e.stride_h);
+  // Channel values of global step gs (step gs % S of block blk0 + gs / S): the
+  // lane's antenna row, users 8 * (2 * step + half) .. +7. Steps past the last
+  // block reload the last one, so every load can be issued unconditionally.
+  constexpr int S = K8 / 2;
+  auto issue = [&](int gs, float (&hr)[8], float (&hi)[8]) {
+    int blk = blk0 + gs / S, st = gs % S;
+    if (blk >= blk1) {
+      blk = blk1 - 1;
+      st = S - 1;
+    }
+    const int mrow = blk * 128 + w * 32 + jl;
+    const bool v = FULL || mrow < e.M;
+    gptr<const float2> hc = Hb + (v ? mrow : 0);
+    const int k8 = 2 * st + half;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int k = 8 * k8 + u;
+      const float2 h = (FULL || (v && k < K)) ? ld2(hc + (int64_t)k * e.ldh) : make_float2(0.f, 0.f);
+      hr[u] = h.x;
+      hi[u] = h.y;
+    }
+  };
+  // Two steps in flight per wave, issued before the X preamble so that their
+  // latency overlaps it.
+  float hrA[8], hiA[8], hrB[8], hiB[8];
+  issue(0, hrA, hiA);
+  issue(1, hrB, hiB);
+
   const float beta = power_factor(e, b);
   if (e.beta_out && mb == 0 && cw == 0 && threadIdx.x == 0) e.beta_out[b] = beta;
 
-  const float2* Xb = e.X + (int64_t)b * e.stride_x;
+  gptr<const float2> Xb = as_global(e.X + (int64_t)b * e.stride_x);
   for (int idx = threadIdx.x; idx < K8 * NC; idx += 256) {
     const int jj = idx % NC, k8 = idx / NC;
     const int j = cw * NC + jj;
@@ -188,7 +224,7 @@ __global__ __launch_bounds__(256) void precoder_bf16_kernel(PrecoderLaunch e) {
     for (int u = 0; u < 8; ++u) {
       const int k = 8 * k8 + u;
       float2 x = make_float2(0.f, 0.f);
-      if (k < K && j < e.nrhs) x = Xb[(int64_t)j * e.ldx + k];
+      if (FULL || (k < K && j < e.nrhs)) x = ld2(Xb + (int64_t)j * e.ldx + k);
       re[u] = beta * x.x;
       im[u] = beta * x.y;
     }
@@ -203,62 +239,57 @@ __global__ __launch_bounds__(256) void precoder_bf16_kernel(PrecoderLaunch e) {
   }
   __syncthreads();
 
+  gptr<float2> Wbase = as_global(e.W_ptrs ? e.W_ptrs[b] : e.W + (int64_t)b * e.stride_w);
+  floatx16 wr[NJ], wi[NJ];
+  // One step: split the staged users, refill the stage with the step two
+  // ahead, then the products of this step's 8 users (per lane half).
+  auto compute = [&](float (&hr)[8], float (&hi)[8], int st, int gs_next) {
+    const int k8 = 2 * st + half;
+    u32x4 Hr[NS], Hi[NS], Hn[NS];
+    split8<NS>(hr, Hr);
+    split8<NS>(hi, Hi);
+    issue(gs_next, hr, hi);
+    __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the products
+#pragma unroll
+    for (int q = 0; q < NS; ++q)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) Hn[q][c] = neg_bf16x2(Hi[q][c]);
+#pragma unroll
+    for (int t = 0; t < NJ; ++t) {
+      u32x4 Xr[NS], Xi[NS];
+#pragma unroll
+      for (int q = 0; q < NS; ++q) {
+        Xr[q] = XS(0, q, k8, t * 32 + jl);
+        Xi[q] = XS(1, q, k8, t * 32 + jl);
+      }
+      split_mma<NS>(Xr, Hr, wr[t]);
+      split_mma<NS>(Xi, Hn, wr[t]);
+      split_mma<NS>(Xr, Hi, wi[t]);
+      split_mma<NS>(Xi, Hr, wi[t]);
+    }
+  };
+  int gs = 0;
 #pragma unroll 1
-  for (int mt = 0; mt < MT; ++mt) {
-    const int m = mb * MB + (mt * 4 + w) * 32 + jl;
-    const bool mvalid = FULL || m < e.M;
-    const float2* hcol = (e.H_ptrs ? e.H_ptrs[b] : e.H + (int64_t)b * e.stride_h) + (mvalid ? m : 0);
-
-    floatx16 wr[NJ], wi[NJ];
+  for (int blk = blk0; blk < blk1; ++blk) {
 #pragma unroll
     for (int t = 0; t < NJ; ++t) {
       wr[t] = zero16();
       wi[t] = zero16();
     }
-    float hr[8], hi[8];
-    auto load_h = [&](int k8) {
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int k = 8 * k8 + u;
-        const float2 h = (FULL || (mvalid && k < K)) ? hcol[(int64_t)k * e.ldh] : make_float2(0.f, 0.f);
-        hr[u] = h.x;
-        hi[u] = h.y;
-      }
-    };
-    load_h(half);
-    for (int step = 0; step < K8 / 2; ++step) {
-      const int k8 = 2 * step + half;
-      u32x4 Hr[NS], Hi[NS], Hn[NS];
-      split8<NS>(hr, Hr);
-      split8<NS>(hi, Hi);
-      if (step + 1 < K8 / 2) load_h(k8 + 2);  // next users in flight during the products
-#pragma unroll
-      for (int q = 0; q < NS; ++q)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) Hn[q][c] = neg_bf16x2(Hi[q][c]);
-#pragma unroll
-      for (int t = 0; t < NJ; ++t) {
-        u32x4 Xr[NS], Xi[NS];
-#pragma unroll
-        for (int q = 0; q < NS; ++q) {
-          Xr[q] = XS(0, q, k8, t * 32 + jl);
-          Xi[q] = XS(1, q, k8, t * 32 + jl);
-        }
-        split_mma<NS>(Xr, Hr, wr[t]);
-        split_mma<NS>(Xi, Hn, wr[t]);
-        split_mma<NS>(Xr, Hi, wi[t]);
-        split_mma<NS>(Xi, Hr, wi[t]);
-      }
+#pragma unroll 1
+    for (int st = 0; st < S; st += 2, gs += 2) {
+      compute(hrA, hiA, st, gs + 2);
+      compute(hrB, hiB, st + 1, gs + 3);
     }
-
-    if (mvalid) {
-      float2* Wb = (e.W_ptrs ? e.W_ptrs[b] : e.W + (int64_t)b * e.stride_w) + m;
+    const int m = blk * 128 + w * 32 + jl;
+    if (FULL || m < e.M) {
+      gptr<float2> Wb = Wbase + m;
 #pragma unroll
       for (int t = 0; t < NJ; ++t) {
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
           const int j = cw * NC + t * 32 + d32_row(r, half);
-          if (FULL || j < e.nrhs) Wb[(int64_t)j * e.ldw] = make_float2(wr[t][r], wi[t][r]);
+          if (FULL || j < e.nrhs) st2(Wb + (int64_t)j * e.ldw, wr[t][r], wi[t][r]);
         }
       }
     }
@@ -267,18 +298,22 @@ __global__ __launch_bounds__(256) void precoder_bf16_kernel(PrecoderLaunch e) {
 
 template <int NS, int KT, int NJ>
 hipError_t launch_bf16_nj(const PrecoderLaunch& e, hipStream_t s) {
-  constexpr int K8 = KT * 4;
-  constexpr int MT = 1;  // antenna tiles per wave (2 doubles the register footprint at K = 64)
-  const int nmb = (e.M + 128 * MT - 1) / (128 * MT);
-  const size_t lds = (size_t)2 * NS * K8 * 32 * NJ * 16;
+  const int nblk = (e.M + 127) / 128;
+  PrecoderLaunch p = e;
+  // Blocks of 128 antennas per workgroup: enough to amortise the split of X,
+  // few enough to keep several workgroups per compute unit busy.
+  if (p.mtiles <= 0) p.mtiles = nblk >= 8 ? 2 : 1;
+  p.mtiles = std::min(p.mtiles, nblk);
+  const int nmb = (nblk + p.mtiles - 1) / p.mtiles;
+  const size_t lds = (size_t)2 * NS * (KT * 4) * 32 * NJ * 16;
   // FULL: every user, antenna and column of every tile is in range (no masks).
-  const bool full = (e.K == KT * 32) && (e.M % (128 * MT) == 0) && (e.nrhs % (32 * NJ) == 0);
+  const bool full = (e.K == KT * 32) && (e.M % 128 == 0) && (e.nrhs % (32 * NJ) == 0);
   const int grid = e.batch * nmb * ((e.nrhs + 32 * NJ - 1) / (32 * NJ));
-  auto kf = precoder_bf16_kernel<NS, KT, NJ, MT, true>;
-  auto km = precoder_bf16_kernel<NS, KT, NJ, MT, false>;
+  auto kf = precoder_bf16_kernel<NS, KT, NJ, true>;
+  auto km = precoder_bf16_kernel<NS, KT, NJ, false>;
   auto k = full ? kf : km;
   if (lds > 65536) (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL(k, dim3(grid), dim3(256), lds, s, e);
+  hipLaunchKernelGGL(k, dim3(grid), dim3(256), lds, s, p);
   return hipGetLastError();
 }
 
