@@ -220,6 +220,42 @@ int rzf_precoder_plain(jacpcg_session* s, void* stream, int batch, int M, int K,
                        jacpcg_c64* W, int64_t ldw, int64_t stride_w,
                        jacpcg_c64* X_out, jacpcg_stats* stats);
 
+/* Per-symbol transmission (eqs. 15-16): for each instance and each of its
+ * nsym symbol vectors s (K x 1), w = A^{-1} s by Jacobi-PCG (or plain CG with
+ * JACPCG_PRECOND_NONE) on A = H^H H + xi I, and the transmitted vector
+ * x = beta_pow H w, with one power factor per instance over its block of
+ * symbols: beta_pow = sqrt(power / ||H W||_F^2), W = [w_1 .. w_nsym], so the
+ * block carries total power `power` (with S = I_K this is rzf_precoder's W;
+ * pass power = nsym * P for an average of P per symbol vector).
+ * S: device, column-major K x nsym c64 per instance (ld lds >= K, stride
+ *   stride_s >= lds * nsym). x: device output, column-major M x nsym per
+ *   instance (ld ldx >= M, stride stride_x >= ldx * nsym). w_out (nullable):
+ *   the solutions, column-major K x nsym (ld K, stride K * nsym).
+ * precision: JACPCG_GRAM_* only (no refinement: E_UNSUPPORTED); tol, max_iter,
+ *   flags and stats as rzf_precoder (per-column iteration counts over the
+ *   nsym columns). Errors: as rzf_precoder; nsym < 1; NULL S or x. */
+int rzf_transmit(jacpcg_session* s, void* stream, int batch, int M, int K, int nsym,
+                 const jacpcg_c64* H, int64_t ldh, int64_t stride_h,
+                 const jacpcg_c64* S, int64_t lds, int64_t stride_s,
+                 double xi, double power, double tol, int max_iter, int precision, int flags,
+                 jacpcg_c64* x, int64_t ldx, int64_t stride_x,
+                 jacpcg_c64* w_out, jacpcg_stats* stats);
+
+/* Evaluation of a precoder on its channel (Sec. II, eqs. 8-10): per user k,
+ *   SINR_k = |h_k^H g_k|^2 / (sum_{j != k} |h_k^H g_j|^2 + sigma2),
+ * and per instance the sum spectral efficiency SE = sum_k log2(1 + SINR_k)
+ * (bit/s/Hz), with g_j column j of W. C = H^H W is formed on the FP32 matrix
+ * cores (session workspace, K x K per instance); every sum has a fixed order.
+ * H, W: device, column-major M x K c64 per instance (as rzf_precoder).
+ * sinr (device, nullable): batch x K floats. se (device, nullable): batch
+ * floats; at least one of them. Asynchronous on `stream`.
+ * Errors: as jacpcg_gram (K <= 256); sigma2 < 0 or non-finite; bad ldw /
+ * stride_w; NULL W; both outputs NULL. */
+int rzf_sinr(jacpcg_session* s, void* stream, int batch, int M, int K,
+             const jacpcg_c64* H, int64_t ldh, int64_t stride_h,
+             const jacpcg_c64* W, int64_t ldw, int64_t stride_w,
+             double sigma2, float* sinr, float* se);
+
 /* ---- request API: continuous batching ---------------------------------- */
 
 /* One precoder request: n_sub subcarrier instances of one (M, K) shape, each

@@ -109,6 +109,11 @@ def _declare(lib):
     lib.rzf_precoder_plain.argtypes = [_vp, _vp, C.c_int, C.c_int, C.c_int, _vp, _i64, _i64, C.c_double,
                                        C.c_double, C.c_double, C.c_int, C.c_int, _vp, _i64, _i64, _vp,
                                        C.POINTER(JacpcgStats)]
+    lib.rzf_transmit.argtypes = [_vp, _vp, C.c_int, C.c_int, C.c_int, C.c_int, _vp, C.c_int64, C.c_int64, _vp,
+                                 C.c_int64, C.c_int64, C.c_double, C.c_double, C.c_double, C.c_int, C.c_int, C.c_int,
+                                 _vp, C.c_int64, C.c_int64, _vp, C.POINTER(JacpcgStats)]
+    lib.rzf_sinr.argtypes = [_vp, _vp, C.c_int, C.c_int, C.c_int, _vp, C.c_int64, C.c_int64, _vp, C.c_int64,
+                             C.c_int64, C.c_double, _vp, _vp]
     lib.jacpcg_session_set_graphs.argtypes = [_vp, C.c_int]
     lib.jacpcg_autotune.argtypes = [_vp, _vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]
     lib.jacpcg_submit.argtypes = [_vp, C.POINTER(JacpcgRequest), C.POINTER(C.c_uint64)]
@@ -118,8 +123,8 @@ def _declare(lib):
     lib.jacpcg_session_clock_us.argtypes = [_vp]
     lib.jacpcg_session_clock_us.restype = C.c_double
     for name in ("jacpcg_session_create", "jacpcg_session_set_profiling", "jacpcg_session_phase_times",
-                 "jacpcg_gram", "jacpcg_solve", "rzf_precoder", "rzf_precoder_plain", "jacpcg_submit", "jacpcg_session_set_graphs", "jacpcg_autotune",
-                 "jacpcg_poll", "jacpcg_wait", "jacpcg_cancel"):
+                 "jacpcg_gram", "jacpcg_solve", "rzf_precoder", "rzf_precoder_plain", "rzf_transmit", "rzf_sinr",
+                 "jacpcg_submit", "jacpcg_session_set_graphs", "jacpcg_autotune", "jacpcg_poll", "jacpcg_wait", "jacpcg_cancel"):
         getattr(lib, name).restype = C.c_int
     return lib
 
@@ -317,6 +322,54 @@ def rzf_precoder_plain(session, H, xi, power=1.0, tol=0.0, max_iter=16, flags=PR
     if stats:
         return W, st.as_dict(), rc
     return W
+
+
+def rzf_transmit(session, H, S, xi, power=1.0, tol=0.0, max_iter=16, precision=GRAM_FP32, flags=PRECOND_JACOBI,
+                 x=None, w_out=None, stats=False, stream=None):
+    """Per-symbol transmission x = beta_pow H A^{-1} s (eqs. 15-16).
+
+    H complex64 [batch, K, M]; S complex64 [batch, nsym, K] (symbol vectors as
+    rows, i.e. column-major K x nsym). Returns x [batch, nsym, M], or
+    (x, stats dict, return code) when stats=True (synchronises)."""
+    torch = _torch()
+    _require(H, "H", torch.complex64)
+    _require(S, "S", torch.complex64)
+    batch, K, M = H.shape
+    if S.dim() != 3 or S.shape[0] != batch or S.shape[2] != K:
+        raise ValueError(f"S must be [batch={batch}, nsym, K={K}], got {tuple(S.shape)}")
+    nsym = S.shape[1]
+    if x is None:
+        x = torch.empty((batch, nsym, M), dtype=torch.complex64, device=H.device)
+    _require(x, "x", torch.complex64, (batch, nsym, M))
+    if w_out is not None:
+        _require(w_out, "w_out", torch.complex64, (batch, nsym, K))
+    st = JacpcgStats() if stats else None
+    rc = _check(lib().rzf_transmit(session.handle, _stream(stream), batch, M, K, nsym, _ptr(H), M, K * M, _ptr(S),
+                                   K, K * nsym, float(xi), float(power), float(tol), int(max_iter), int(precision),
+                                   int(flags), _ptr(x), M, M * nsym, _ptr(w_out),
+                                   C.byref(st) if st is not None else None))
+    if stats:
+        return x, st.as_dict(), rc
+    return x
+
+
+def rzf_sinr(session, H, W, sigma2, sinr=None, se=None, stream=None):
+    """Per-user SINR and per-instance sum rate of precoder W on channel H
+    (eqs. 8-10). H, W complex64 [batch, K, M]. Returns (sinr [batch, K],
+    se [batch]) as float32 device tensors."""
+    torch = _torch()
+    _require(H, "H", torch.complex64)
+    batch, K, M = H.shape
+    _require(W, "W", torch.complex64, (batch, K, M))
+    if sinr is None:
+        sinr = torch.empty((batch, K), dtype=torch.float32, device=H.device)
+    if se is None:
+        se = torch.empty((batch,), dtype=torch.float32, device=H.device)
+    _require(sinr, "sinr", torch.float32, (batch, K))
+    _require(se, "se", torch.float32, (batch,))
+    _check(lib().rzf_sinr(session.handle, _stream(stream), batch, M, K, _ptr(H), M, K * M, _ptr(W), M, K * M,
+                          float(sigma2), _ptr(sinr), _ptr(se)))
+    return sinr, se
 
 
 def jacpcg_submit(session, H, W, xi, power=1.0, tol=0.0, max_iter=16, precision=GRAM_FP32, flags=PRECOND_JACOBI,

@@ -299,9 +299,45 @@ int rzf_precoder(jacpcg_session* s, void* stream, int batch, int M, int K, const
   }
   JP_HIP(hipSetDevice(s->device));
   hipStream_t st = (hipStream_t)stream;
-  return s->run_rzf(st, batch, M, K, (const float2*)H, ldh, stride_h, xi, power, tol, max_iter, gram_prec, refine,
-                    (flags & JACPCG_PRECOND_NONE) != 0, (flags & JACPCG_EPILOGUE_FP32) == 0, refine_tol,
-                    (float2*)W, ldw, stride_w, (float2*)X_out, (double2*)X64_out, stats);
+  return s->run_rzf(st, batch, M, K, (const float2*)H, ldh, stride_h, K, nullptr, 0, 0, xi, power, tol, max_iter,
+                    gram_prec, refine, (flags & JACPCG_PRECOND_NONE) != 0, (flags & JACPCG_EPILOGUE_FP32) == 0,
+                    refine_tol, (float2*)W, ldw, stride_w, (float2*)X_out, (double2*)X64_out, stats);
+}
+
+int rzf_transmit(jacpcg_session* s, void* stream, int batch, int M, int K, int nsym, const jacpcg_c64* H,
+                 int64_t ldh, int64_t stride_h, const jacpcg_c64* S, int64_t lds, int64_t stride_s, double xi,
+                 double power, double tol, int max_iter, int precision, int flags, jacpcg_c64* x, int64_t ldx,
+                 int64_t stride_x, jacpcg_c64* w_out, jacpcg_stats* stats) {
+  int rc = check_gram_args(batch, M, K, H, ldh, stride_h, xi, nullptr, 0, 0);
+  if (rc) return rc;
+  JP_CHECK(nsym >= 1, "nsym must be >= 1 (got %d)", nsym);
+  JP_CHECK(std::isfinite(power) && power > 0.0, "power must be finite and > 0 (got %g)", power);
+  JP_CHECK(std::isfinite(tol) && tol >= 0.0, "tol must be finite and >= 0 (got %g)", tol);
+  JP_CHECK(max_iter >= 0, "max_iter must be >= 0 (got %d)", max_iter);
+  JP_CHECK((flags & ~(JACPCG_PRECOND_NONE | JACPCG_EPILOGUE_FP32)) == 0, "unknown flags 0x%x", flags);
+  JP_CHECK(lds >= K, "lds must be >= K (got %lld < %d)", (long long)lds, K);
+  if (batch > 1) JP_CHECK(stride_s >= lds * nsym, "stride_s must be >= lds * nsym");
+  JP_CHECK(ldx >= M, "ldx must be >= M (got %lld < %d)", (long long)ldx, M);
+  if (batch > 1) JP_CHECK(stride_x >= ldx * nsym, "stride_x must be >= ldx * nsym");
+  if (batch > 0) {
+    JP_CHECK(S != nullptr, "S is NULL");
+    JP_CHECK(x != nullptr, "x is NULL");
+  }
+  if ((precision & ~0xff) != 0)
+    return fail(JACPCG_E_UNSUPPORTED, "rzf_transmit takes an FP32 or split-BF16 Gram, no refinement (0x%x)",
+                precision);
+  if ((precision & 0xff) > 2) return fail(JACPCG_E_UNSUPPORTED, "unknown precision 0x%x", precision);
+  rc = check_session(s);
+  if (rc) return rc;
+  if (batch == 0) {
+    if (stats) std::memset(stats, 0, sizeof *stats);
+    return JACPCG_OK;
+  }
+  JP_HIP(hipSetDevice(s->device));
+  return s->run_rzf((hipStream_t)stream, batch, M, K, (const float2*)H, ldh, stride_h, nsym, (const float2*)S, lds,
+                    stride_s, xi, power, tol, max_iter, precision & 0xff, false, (flags & JACPCG_PRECOND_NONE) != 0,
+                    (flags & JACPCG_EPILOGUE_FP32) == 0, 0.0, (float2*)x, ldx, stride_x, (float2*)w_out, nullptr,
+                    stats);
 }
 
 int rzf_precoder_plain(jacpcg_session* s, void* stream, int batch, int M, int K, const jacpcg_c64* H, int64_t ldh,
@@ -326,6 +362,26 @@ int rzf_precoder_plain(jacpcg_session* s, void* stream, int batch, int M, int K,
   return s->run_rzf_plain((hipStream_t)stream, batch, M, K, (const float2*)H, ldh, stride_h, xi, power, tol,
                           max_iter, (flags & JACPCG_PRECOND_NONE) != 0, (flags & JACPCG_EPILOGUE_FP32) == 0,
                           (float2*)W, ldw, stride_w, (float2*)X_out, stats);
+}
+
+int rzf_sinr(jacpcg_session* s, void* stream, int batch, int M, int K, const jacpcg_c64* H, int64_t ldh,
+             int64_t stride_h, const jacpcg_c64* W, int64_t ldw, int64_t stride_w, double sigma2, float* sinr,
+             float* se) {
+  int rc = check_gram_args(batch, M, K, H, ldh, stride_h, 0.0, nullptr, 0, 0);
+  if (rc) return rc;
+  JP_CHECK(std::isfinite(sigma2) && sigma2 >= 0.0, "sigma2 must be finite and >= 0 (got %g)", sigma2);
+  JP_CHECK(ldw >= M, "ldw must be >= M (got %lld < %d)", (long long)ldw, M);
+  if (batch > 1) JP_CHECK(stride_w >= ldw * K, "stride_w must be >= ldw * K");
+  if (batch > 0) {
+    JP_CHECK(W != nullptr, "W is NULL");
+    JP_CHECK(sinr != nullptr || se != nullptr, "sinr and se are both NULL");
+  }
+  rc = check_session(s);
+  if (rc) return rc;
+  if (batch == 0) return JACPCG_OK;
+  JP_HIP(hipSetDevice(s->device));
+  return s->run_sinr((hipStream_t)stream, batch, M, K, (const float2*)H, ldh, stride_h, (const float2*)W, ldw,
+                     stride_w, sigma2, sinr, se);
 }
 
 int jacpcg_session_set_graphs(jacpcg_session* s, int enable) {

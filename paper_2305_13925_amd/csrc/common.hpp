@@ -118,6 +118,17 @@ struct AccumulateLaunch {
   float2* X32;                              // nullable: rounded copy of the result
 };
 
+// Precoder evaluation (eqs. 8-10): C = H^H W, per-user SINR, sum rate.
+struct EvalLaunch {
+  const float2* H; int64_t ldh, stride_h;
+  const float2* W; int64_t ldw, stride_w;
+  int batch, M, K;
+  float sigma2;
+  float2* C;                                // workspace: batch x K x K row-major, C[k][j] = h_k^H w_j
+  float* sinr;                              // batch x K
+  float* se;                                // batch (nullable): sum_k log2(1 + SINR_k)
+};
+
 // Kernel launchers (defined in the .hip files). All return hipError_t of the
 // launch itself.
 hipError_t launch_gram(const GramLaunch& g, hipStream_t s);
@@ -131,6 +142,7 @@ hipError_t launch_residual(const ResidualLaunch& r, hipStream_t s);
 hipError_t launch_accumulate(const AccumulateLaunch& a, hipStream_t s);
 int residual_workgroups_per_instance(int nrhs);
 hipError_t launch_fill_synthetic(float2* H, size_t n, uint32_t seed, hipStream_t s);
+hipError_t launch_eval(const EvalLaunch& e, hipStream_t s);
 hipError_t launch_widen(const float2* X, int64_t ldx, int64_t stride_x, int batch, int K, int n,
                         double2* out, hipStream_t s);
 

@@ -156,21 +156,23 @@ void jacpcg_session::shutdown() {
 // Batched path: Gram -> persistent PCG (+ ||H X||^2 pass) -> precoder.
 // ---------------------------------------------------------------------------
 int jacpcg_session::run_rzf(hipStream_t st, int batch, int M, int K, const float2* H, int64_t ldh, int64_t stride_h,
-                            double xi, double power, double tol, int max_iter, int gram_prec, bool refine,
-                            bool precond_none, bool split_epilogue, double refine_tol, float2* W, int64_t ldw,
-                            int64_t stride_w,
+                            int nrhs, const float2* B, int64_t ldb, int64_t stride_b, double xi, double power,
+                            double tol, int max_iter, int gram_prec, bool refine, bool precond_none,
+                            bool split_epilogue, double refine_tol, float2* W, int64_t ldw, int64_t stride_w,
                             float2* X_out, double2* X64_out, jacpcg_stats* stats) {
-  const int ncb = (K + 31) / 32;
+  // nrhs right-hand-side columns (B = NULL: the identity, nrhs = K).
+  const int ncb = (nrhs + 31) / 32;
   const size_t KK = (size_t)K * K;
+  const size_t KN = (size_t)K * nrhs;
   Workspace ws;
   const size_t oA = ws.take<float2>(batch * KK);
   const size_t oG = ws.take<float>((size_t)batch * K);
-  const size_t oX = X_out ? 0 : ws.take<float2>(batch * KK);
+  const size_t oX = X_out ? 0 : ws.take<float2>(batch * KN);
   const size_t oF = ws.take<float>((size_t)batch * ncb);
   const size_t oWG = ws.take<int32_t>((size_t)batch * ncb);
   const size_t oS = ws.take<int32_t>(batch);
-  const size_t oI = ws.take<int32_t>((size_t)batch * K);
-  const size_t oR = ws.take<float>((size_t)batch * K);
+  const size_t oI = ws.take<int32_t>((size_t)batch * nrhs);
+  const size_t oR = ws.take<float>((size_t)batch * nrhs);
   const size_t oB = ws.take<float>(batch);
   // refinement buffers
   const int n16 = residual_workgroups_per_instance(K);
@@ -220,13 +222,15 @@ int jacpcg_session::run_rzf(hipStream_t st, int batch, int M, int K, const float
     p.A = A;
     p.lda = K;
     p.stride_a = (int64_t)KK;
-    p.B = nullptr;
+    p.B = B;
+    p.ldb = ldb;
+    p.stride_b = stride_b;
     p.X = X;
     p.ldx = K;
-    p.stride_x = (int64_t)KK;
+    p.stride_x = (int64_t)KN;
     p.batch = batch;
     p.K = K;
-    p.nrhs = K;
+    p.nrhs = nrhs;
     p.tol = (float)tol;
     p.max_iter = max_iter;
     p.precond_none = precond_none;
@@ -249,14 +253,14 @@ int jacpcg_session::run_rzf(hipStream_t st, int batch, int M, int K, const float
     E.stride_h = stride_h;
     E.X = X;
     E.ldx = K;
-    E.stride_x = (int64_t)KK;
+    E.stride_x = (int64_t)KN;
     E.W = W;
     E.ldw = ldw;
     E.stride_w = stride_w;
     E.batch = batch;
     E.M = M;
     E.K = K;
-    E.nrhs = K;
+    E.nrhs = nrhs;
     E.fpart = fpart;
     E.ncb = ncb;
     E.power = (float)power;
@@ -268,14 +272,15 @@ int jacpcg_session::run_rzf(hipStream_t st, int batch, int M, int K, const float
     hipError_t e = timed_run ? timed(q, JACPCG_PHASE_EPILOGUE, [&] { return launch_precoder(E, q); })
                              : launch_precoder(E, q);
     if (e != hipSuccess) return e;
-    if (X64_out && !refine) e = launch_widen(X, K, (int64_t)KK, batch, K, K, X64_out, q);
+    if (X64_out && !refine) e = launch_widen(X, K, (int64_t)KN, batch, K, nrhs, X64_out, q);
     return e;
   };
 
   // Repeated calls with identical arguments replay one captured HIP graph
   // (captured on a side stream, launched on the caller's stream).
   if (!refine && !stats && use_graphs && !profiling) {
-    const uint64_t key = graph_key({(uint64_t)batch, (uint64_t)M, (uint64_t)K, (uint64_t)(uintptr_t)H,
+    const uint64_t key = graph_key({(uint64_t)batch, (uint64_t)M, (uint64_t)K, (uint64_t)nrhs,
+                                    (uint64_t)(uintptr_t)B, (uint64_t)ldb, (uint64_t)stride_b, (uint64_t)(uintptr_t)H,
                                     (uint64_t)ldh, (uint64_t)stride_h, bits_of(xi), bits_of(power), bits_of(tol),
                                     (uint64_t)max_iter, (uint64_t)gram_prec, (uint64_t)precond_none,
                                     (uint64_t)split_epilogue, (uint64_t)(uintptr_t)W, (uint64_t)ldw,
@@ -387,23 +392,51 @@ int jacpcg_session::run_rzf(hipStream_t st, int batch, int M, int K, const float
   jacpcg_stats local_stats;
   if (!stats && refine) stats = &local_stats;  // the refined path synchronises anyway
   if (!stats) return JACPCG_OK;
-  const size_t hb = (size_t)batch * K * 8 + (size_t)batch * 8;
+  const size_t hb = (size_t)batch * nrhs * 8 + (size_t)batch * 8;
   char* h = (char*)host_scratch(hb);
   if (!h) return set_error(JACPCG_E_OUT_OF_MEMORY, "pinned host staging allocation failed");
   int32_t* h_it = (int32_t*)h;
-  float* h_rr = (float*)(h_it + (size_t)batch * K);
-  int32_t* h_st = (int32_t*)(h_rr + (size_t)batch * K);
+  float* h_rr = (float*)(h_it + (size_t)batch * nrhs);
+  int32_t* h_st = (int32_t*)(h_rr + (size_t)batch * nrhs);
   float* h_b = (float*)(h_st + batch);
-  S_HIP(hipMemcpyAsync(h_it, iters, (size_t)batch * K * 4, hipMemcpyDeviceToHost, st));
-  S_HIP(hipMemcpyAsync(h_rr, relres, (size_t)batch * K * 4, hipMemcpyDeviceToHost, st));
+  S_HIP(hipMemcpyAsync(h_it, iters, (size_t)batch * nrhs * 4, hipMemcpyDeviceToHost, st));
+  S_HIP(hipMemcpyAsync(h_rr, relres, (size_t)batch * nrhs * 4, hipMemcpyDeviceToHost, st));
   S_HIP(hipMemcpyAsync(h_st, status, (size_t)batch * 4, hipMemcpyDeviceToHost, st));
   S_HIP(hipMemcpyAsync(h_b, beta, (size_t)batch * 4, hipMemcpyDeviceToHost, st));
   S_HIP(hipStreamSynchronize(st));
-  fill_stats_host(stats, batch, K, h_it, h_rr, h_st, h_b);
+  fill_stats_host(stats, batch, nrhs, h_it, h_rr, h_st, h_b);
   stats->refine_steps = refine_steps;
   stats->max_refine_residual = refine_res;
   if (refine && refine_res > refine_tol && stats->worst_status == JACPCG_OK) stats->worst_status = JACPCG_NOT_CONVERGED;
   return stats->worst_status;
+}
+
+// ---------------------------------------------------------------------------
+// Precoder evaluation: C = H^H W, per-user SINR and sum rate.
+// ---------------------------------------------------------------------------
+int jacpcg_session::run_sinr(hipStream_t st, int batch, int M, int K, const float2* H, int64_t ldh,
+                             int64_t stride_h, const float2* W, int64_t ldw, int64_t stride_w, double sigma2,
+                             float* sinr, float* se) {
+  Workspace ws;
+  const size_t oC = ws.take<float2>((size_t)batch * K * K);
+  const size_t oS = sinr ? 0 : ws.take<float>((size_t)batch * K);
+  if (int rc = reserve(ws)) return rc;
+  EvalLaunch e{};
+  e.H = H;
+  e.ldh = ldh;
+  e.stride_h = stride_h;
+  e.W = W;
+  e.ldw = ldw;
+  e.stride_w = stride_w;
+  e.batch = batch;
+  e.M = M;
+  e.K = K;
+  e.sigma2 = (float)sigma2;
+  e.C = at<float2>(oC);
+  e.sinr = sinr ? sinr : at<float>(oS);
+  e.se = se;
+  S_HIP(launch_eval(e, st));
+  return JACPCG_OK;
 }
 
 // ---------------------------------------------------------------------------

@@ -101,10 +101,12 @@ struct jacpcg_session {
   hipError_t collect_events();
   void shutdown();
 
-  int run_rzf(hipStream_t st, int batch, int M, int K, const float2* H, int64_t ldh, int64_t stride_h, double xi,
-              double power, double tol, int max_iter, int gram_prec, bool refine, bool precond_none,
-              bool split_epilogue, double refine_tol, float2* W, int64_t ldw, int64_t stride_w, float2* X_out, double2* X64_out,
-              jacpcg_stats* stats);
+  int run_rzf(hipStream_t st, int batch, int M, int K, const float2* H, int64_t ldh, int64_t stride_h, int nrhs,
+              const float2* B, int64_t ldb, int64_t stride_b, double xi, double power, double tol, int max_iter,
+              int gram_prec, bool refine, bool precond_none, bool split_epilogue, double refine_tol, float2* W,
+              int64_t ldw, int64_t stride_w, float2* X_out, double2* X64_out, jacpcg_stats* stats);
+  int run_sinr(hipStream_t st, int batch, int M, int K, const float2* H, int64_t ldh, int64_t stride_h,
+               const float2* W, int64_t ldw, int64_t stride_w, double sigma2, float* sinr, float* se);
   int run_rzf_plain(hipStream_t st, int batch, int M, int K, const float2* H, int64_t ldh, int64_t stride_h,
                     double xi, double power, double tol, int max_iter, bool precond_none, bool split_epilogue,
                     float2* W, int64_t ldw,

@@ -111,6 +111,46 @@ def test_rzf_unknown_precision():
     assert _rzf(prec=0x1000) == bd.E_UNSUPPORTED
 
 
+def _tx(**kw):
+    a = dict(batch=2, M=32, K=4, n=3, H=FAKE, ldh=32, sh=128, S=FAKE, lds=4, ss=12, xi=0.5, power=1.0, tol=0.0,
+             it=4, prec=0, flags=0, x=FAKE, ldx=32, sx=96)
+    a.update(kw)
+    return L.rzf_transmit(NULL, NULL, a["batch"], a["M"], a["K"], a["n"], a["H"], a["ldh"], a["sh"], a["S"],
+                          a["lds"], a["ss"], a["xi"], a["power"], a["tol"], a["it"], a["prec"], a["flags"], a["x"],
+                          a["ldx"], a["sx"], NULL, NULL)
+
+
+@pytest.mark.parametrize("kw,word", [
+    (dict(n=0), "nsym"), (dict(S=NULL), "S"), (dict(x=NULL), "x"), (dict(lds=3), "lds"),
+    (dict(ss=11), "stride_s"), (dict(ldx=31), "ldx"), (dict(sx=95), "stride_x"), (dict(power=0.0), "power"),
+    (dict(flags=4), "flags"), (dict(K=0), "K"),
+])
+def test_transmit_validation(kw, word):
+    assert _tx(**kw) == bd.E_INVALID_ARG
+    assert word in _err()
+
+
+def test_transmit_rejects_refinement():
+    assert _tx(prec=0x100) == bd.E_UNSUPPORTED
+    assert _tx(prec=0x3) == bd.E_UNSUPPORTED
+
+
+def _sinr(**kw):
+    a = dict(batch=2, M=32, K=4, H=FAKE, ldh=32, sh=128, W=FAKE, ldw=32, sw=128, s2=0.1, sinr=FAKE, se=FAKE)
+    a.update(kw)
+    return L.rzf_sinr(NULL, NULL, a["batch"], a["M"], a["K"], a["H"], a["ldh"], a["sh"], a["W"], a["ldw"], a["sw"],
+                      a["s2"], a["sinr"], a["se"])
+
+
+@pytest.mark.parametrize("kw,word", [
+    (dict(s2=-1.0), "sigma2"), (dict(s2=float("nan")), "sigma2"), (dict(W=NULL), "W"), (dict(ldw=31), "ldw"),
+    (dict(sw=127), "stride_w"), (dict(sinr=NULL, se=NULL), "NULL"), (dict(K=257), "K"), (dict(H=NULL), "H"),
+])
+def test_sinr_validation(kw, word):
+    assert _sinr(**kw) == bd.E_INVALID_ARG
+    assert word in _err()
+
+
 def test_plain_validation():
     rc = L.rzf_precoder_plain(NULL, NULL, 1, 32, 300, FAKE, 32, 0, 0.5, 1.0, 0.0, 4, 0, FAKE, 32, 0, NULL, NULL)
     assert rc == bd.E_INVALID_ARG and "K" in _err()

@@ -175,3 +175,19 @@ def test_literal_algorithm1_coincides_only_for_constant_diagonal(rng):
     std = oracle.jacpcg(Avar, b, tol=0.0, max_iter=8)["X"][:, 0]
     assert np.linalg.norm(lit - std) > 1e-6 * np.linalg.norm(std)
     assert np.linalg.norm(std - np.linalg.solve(Avar, b)) < 1e-9 * np.linalg.norm(std)
+
+
+def test_jacobi_needs_fewer_iterations_than_cg():
+    # The paper's convergence comparison (Sec. IV, Fig. 2): Jacobi
+    # preconditioning (eq. 21) beats plain CG when the users' gains -- the
+    # diagonal of A -- are spread, as in the gain-normalised channels.
+    from channelgen import channel_batch, workload
+    w = workload("single", gain="normalised")
+    H = channel_batch(w, n=6)
+    jac, cg = [], []
+    for b in range(6):
+        A = oracle.gram(H[b].T.astype(np.complex128), w.xi_values()[0])
+        s = np.ones((w.K, 1), np.complex128)
+        jac.append(int(oracle.jacpcg(A, s, tol=1e-6, max_iter=500)["iters"][0]))
+        cg.append(int(oracle.jacpcg(A, s, tol=1e-6, max_iter=500, precond="none")["iters"][0]))
+    assert all(j < c for j, c in zip(jac, cg)), (jac, cg)
