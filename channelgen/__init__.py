@@ -16,4 +16,6 @@ from .xlmimo import (  # noqa: F401
     request_channels,
     instance_matrix,
     device_pool,
+    block_channel_instance,
+    block_channel_batch,
 )

@@ -147,6 +147,37 @@ def instance_matrix(Hb):
     return np.asarray(Hb).T.astype(np.complex128)
 
 
+def block_channel_instance(M1, Mc, M2, K1, K2, r, seed, index, gain="normalised"):
+    """One channel of the subarray-block form of eq. 2 (three subarrays, two
+    user groups): group 1 (K1 users) sees subarray 1 (M1 antennas) and the
+    common subarray (Mc), group 2 (K2 users) sees the common subarray and
+    subarray 2 (M2); every other block is zero (outside the users' visibility
+    regions). Within a subarray the antennas are exponentially correlated with
+    coefficient r (AR(1) recursion); the per-user gain follows ``gain`` as in
+    ``channel_instance``. Returns complex64 [K1 + K2, M1 + Mc + M2].
+    """
+    K, M = K1 + K2, M1 + Mc + M2
+    rng = _rng(seed, index)
+    d = rng.uniform(10.0, 100.0, size=K)
+    beta = d ** -3.7 if gain == "literal" else (d / 10.0) ** -3.7
+    h = np.zeros((K, M), dtype=np.complex128)
+    spans = {"1": (0, M1), "c": (M1, M1 + Mc), "2": (M1 + Mc, M)}
+    for k in range(K):
+        for sub in (("1", "c") if k < K1 else ("c", "2")):
+            a, b = spans[sub]
+            if b == a:
+                continue
+            g = (rng.standard_normal(b - a) + 1j * rng.standard_normal(b - a)) / np.sqrt(2.0)
+            h[k, a:b] = _ar1_factor(b - a, r) @ g
+    h *= np.sqrt(beta)[:, None]
+    return h.astype(np.complex64)
+
+
+def block_channel_batch(M1, Mc, M2, K1, K2, r, n, seed=0, gain="normalised"):
+    """Instances 0 .. n-1 of the block channel model as complex64 [n, K1 + K2, M]."""
+    return np.stack([block_channel_instance(M1, Mc, M2, K1, K2, r, seed, i, gain) for i in range(n)])
+
+
 def serving_requests(rate_hz=2000.0, duration_s=11.0, seed=0, max_requests=None):
     """Poisson request stream of the serving workload.
 

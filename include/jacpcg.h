@@ -241,6 +241,25 @@ int rzf_transmit(jacpcg_session* s, void* stream, int batch, int M, int K, int n
                  jacpcg_c64* x, int64_t ldx, int64_t stride_x,
                  jacpcg_c64* w_out, jacpcg_stats* stats);
 
+/* Subarray-block RZF (Sec. II, eqs. 2, 6 and 7): three subarrays of M1, Mc
+ * and M2 antennas (rows [0, M1), [M1, M1+Mc), [M1+Mc, M)), two user groups of
+ * K1 and K2 users (columns [0, K1), [K1, K)); group 1 sees subarrays 1 and c,
+ * group 2 sees c and 2, so H has the block form of eq. 2 (the caller's other
+ * blocks are never read). Each block is its own RZF problem with its own
+ * power factor (eq. 7): G_1 = beta_1 H_1 P_1^{-1} (M1 x K1), G_c =
+ * beta_c H_c P_c^{-1} (Mc x K), G_2 = beta_2 H_2 P_2^{-1} (M2 x K2), each of
+ * total power `power`; the other two blocks of G are written as zeros (eq. 6).
+ * H, G: device, column-major M x K c64 per instance (ld ldh / ldg >= M,
+ * strides >= ld * K). Blocks with no rows or no users are skipped.
+ * Every other argument as rzf_precoder; stats (when given) combine the three
+ * solves (maxima, worst status). Runs as three batched precoder solves on
+ * `stream`. Errors: as rzf_precoder; negative sizes; K > 256. */
+int rzf_block_precoder(jacpcg_session* s, void* stream, int batch, int M1, int Mc, int M2, int K1, int K2,
+                       const jacpcg_c64* H, int64_t ldh, int64_t stride_h,
+                       double xi, double power, double tol, int max_iter, int precision, int flags,
+                       double refine_tol, jacpcg_c64* G, int64_t ldg, int64_t stride_g,
+                       jacpcg_stats* stats);
+
 /* Evaluation of a precoder on its channel (Sec. II, eqs. 8-10): per user k,
  *   SINR_k = |h_k^H g_k|^2 / (sum_{j != k} |h_k^H g_j|^2 + sigma2),
  * and per instance the sum spectral efficiency SE = sum_k log2(1 + SINR_k)

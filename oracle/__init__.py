@@ -28,6 +28,8 @@ from .rzf import (  # noqa: F401
     jacpcg_alg1_literal,
     precoder,
     rzf,
+    block_slices,
+    block_rzf,
     direct_rzf,
     sinr,
     sum_rate,

@@ -286,6 +286,50 @@ def direct_rzf(H, xi, B=None, P_tx=1.0):
 
 
 # ---------------------------------------------------------------------------
+# O6: subarray-block RZF (Sec. II: eqs. 2, 6 and 7)
+# ---------------------------------------------------------------------------
+def block_slices(M1, Mc, M2, K1, K2):
+    """Row and column ranges of the three blocks of eq. 2 / eq. 6.
+
+    Antennas: subarray 1 = rows [0, M1), the common subarray c = rows
+    [M1, M1 + Mc), subarray 2 = rows [M1 + Mc, M1 + Mc + M2). Users: group 1 =
+    columns [0, K1), group 2 = columns [K1, K1 + K2). Returns a dict
+    block -> (row slice, column slice) for blocks "1", "c", "2".
+    """
+    r1, rc, r2 = slice(0, M1), slice(M1, M1 + Mc), slice(M1 + Mc, M1 + Mc + M2)
+    return {"1": (r1, slice(0, K1)), "c": (rc, slice(0, K1 + K2)), "2": (r2, slice(K1, K1 + K2))}
+
+
+def block_rzf(H, xi, M1, Mc, M2, K1, K2, tol=0.0, max_iter=16, P_tx=1.0, precond="jacobi", direct=False):
+    """Subarray-block RZF precoder G of eq. 6 for a channel H of the form of eq. 2.
+
+    Each block i in {1, c, 2} is its own RZF problem (eq. 7):
+    G_i = beta_i H_i P_i^{-1}, P_i = H_i^H H_i + xi I, with its own power factor
+    beta_i = sqrt(P_tx / tr(F_i^H F_i)). G_1 and G_2 fill the (subarray 1,
+    group 1) and (subarray 2, group 2) blocks, G_c = [G_c1, G_c2] the common
+    subarray's rows; the (subarray 1, group 2) and (subarray 2, group 1)
+    blocks are zero. P_i^{-1} comes from Jacobi-PCG (O3) at (tol, max_iter),
+    or from the Cholesky inverse when ``direct``. Returns (G, {block: beta_i}).
+    """
+    H = _c128(H)
+    G = np.zeros_like(H)
+    betas = {}
+    for name, (rows, cols) in block_slices(M1, Mc, M2, K1, K2).items():
+        Hi = H[rows, cols]
+        if Hi.size == 0:
+            betas[name] = 0.0
+            continue
+        if direct:
+            _, Gi, beta = direct_rzf(Hi, xi, P_tx=P_tx)
+        else:
+            r = rzf(Hi, xi, tol=tol, max_iter=max_iter, P_tx=P_tx, precond=precond)
+            Gi, beta = r["W"], r["beta_pow"]
+        G[rows, cols] = Gi
+        betas[name] = beta
+    return G, betas
+
+
+# ---------------------------------------------------------------------------
 # Application-level evaluation (eqs. 9-10)
 # ---------------------------------------------------------------------------
 def sinr(H, W, sigma2):

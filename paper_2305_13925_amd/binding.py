@@ -112,6 +112,9 @@ def _declare(lib):
     lib.rzf_transmit.argtypes = [_vp, _vp, C.c_int, C.c_int, C.c_int, C.c_int, _vp, C.c_int64, C.c_int64, _vp,
                                  C.c_int64, C.c_int64, C.c_double, C.c_double, C.c_double, C.c_int, C.c_int, C.c_int,
                                  _vp, C.c_int64, C.c_int64, _vp, C.POINTER(JacpcgStats)]
+    lib.rzf_block_precoder.argtypes = [_vp, _vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, _vp,
+                                       C.c_int64, C.c_int64, C.c_double, C.c_double, C.c_double, C.c_int, C.c_int,
+                                       C.c_int, C.c_double, _vp, C.c_int64, C.c_int64, C.POINTER(JacpcgStats)]
     lib.rzf_sinr.argtypes = [_vp, _vp, C.c_int, C.c_int, C.c_int, _vp, C.c_int64, C.c_int64, _vp, C.c_int64,
                              C.c_int64, C.c_double, _vp, _vp]
     lib.jacpcg_session_set_graphs.argtypes = [_vp, C.c_int]
@@ -124,7 +127,8 @@ def _declare(lib):
     lib.jacpcg_session_clock_us.restype = C.c_double
     for name in ("jacpcg_session_create", "jacpcg_session_set_profiling", "jacpcg_session_phase_times",
                  "jacpcg_gram", "jacpcg_solve", "rzf_precoder", "rzf_precoder_plain", "rzf_transmit", "rzf_sinr",
-                 "jacpcg_submit", "jacpcg_session_set_graphs", "jacpcg_autotune", "jacpcg_poll", "jacpcg_wait", "jacpcg_cancel"):
+                 "rzf_block_precoder", "jacpcg_submit", "jacpcg_session_set_graphs", "jacpcg_autotune",
+                 "jacpcg_poll", "jacpcg_wait", "jacpcg_cancel"):
         getattr(lib, name).restype = C.c_int
     return lib
 
@@ -351,6 +355,29 @@ def rzf_transmit(session, H, S, xi, power=1.0, tol=0.0, max_iter=16, precision=G
     if stats:
         return x, st.as_dict(), rc
     return x
+
+
+def rzf_block_precoder(session, H, xi, M1, Mc, M2, K1, K2, power=1.0, tol=0.0, max_iter=16, precision=GRAM_FP32,
+                       flags=PRECOND_JACOBI, refine_tol=1e-10, G=None, stats=False, stream=None):
+    """Subarray-block RZF G (eqs. 2, 6, 7) for H complex64 [batch, K1 + K2, M1 + Mc + M2].
+
+    Returns G of the same shape, or (G, stats dict, return code) when stats=True."""
+    torch = _torch()
+    _require(H, "H", torch.complex64)
+    batch, K, M = H.shape
+    if M != M1 + Mc + M2 or K != K1 + K2:
+        raise ValueError(f"H is [batch, {K}, {M}], blocks give K = {K1 + K2}, M = {M1 + Mc + M2}")
+    if G is None:
+        G = torch.empty_like(H)
+    _require(G, "G", torch.complex64, (batch, K, M))
+    st = JacpcgStats() if stats else None
+    rc = _check(lib().rzf_block_precoder(session.handle, _stream(stream), batch, int(M1), int(Mc), int(M2), int(K1),
+                                         int(K2), _ptr(H), M, K * M, float(xi), float(power), float(tol),
+                                         int(max_iter), int(precision), int(flags), float(refine_tol), _ptr(G), M,
+                                         K * M, C.byref(st) if st is not None else None))
+    if stats:
+        return G, st.as_dict(), rc
+    return G
 
 
 def rzf_sinr(session, H, W, sigma2, sinr=None, se=None, stream=None):

@@ -364,6 +364,39 @@ int rzf_precoder_plain(jacpcg_session* s, void* stream, int batch, int M, int K,
                           (float2*)W, ldw, stride_w, (float2*)X_out, stats);
 }
 
+int rzf_block_precoder(jacpcg_session* s, void* stream, int batch, int M1, int Mc, int M2, int K1, int K2,
+                       const jacpcg_c64* H, int64_t ldh, int64_t stride_h, double xi, double power, double tol,
+                       int max_iter, int precision, int flags, double refine_tol, jacpcg_c64* G, int64_t ldg,
+                       int64_t stride_g, jacpcg_stats* stats) {
+  JP_CHECK(M1 >= 0 && Mc >= 0 && M2 >= 0, "subarray sizes must be >= 0 (got %d, %d, %d)", M1, Mc, M2);
+  JP_CHECK(K1 >= 0 && K2 >= 0, "group sizes must be >= 0 (got %d, %d)", K1, K2);
+  const int M = M1 + Mc + M2, K = K1 + K2;
+  int rc = check_gram_args(batch, M, K, H, ldh, stride_h, xi, nullptr, 0, 0);
+  if (rc) return rc;
+  JP_CHECK(std::isfinite(power) && power > 0.0, "power must be finite and > 0 (got %g)", power);
+  JP_CHECK(std::isfinite(tol) && tol >= 0.0, "tol must be finite and >= 0 (got %g)", tol);
+  JP_CHECK(max_iter >= 0, "max_iter must be >= 0 (got %d)", max_iter);
+  JP_CHECK((flags & ~(JACPCG_PRECOND_NONE | JACPCG_EPILOGUE_FP32)) == 0, "unknown flags 0x%x", flags);
+  JP_CHECK(std::isfinite(refine_tol) && refine_tol >= 0.0, "refine_tol must be finite and >= 0");
+  JP_CHECK(ldg >= M, "ldg must be >= M1 + Mc + M2 (got %lld < %d)", (long long)ldg, M);
+  if (batch > 1) JP_CHECK(stride_g >= ldg * K, "stride_g must be >= ldg * (K1 + K2)");
+  if (batch > 0) JP_CHECK(G != nullptr, "G is NULL");
+  const int gram_prec = precision & 0xff;
+  const bool refine = (precision & JACPCG_REFINE_FP64) != 0;
+  if (gram_prec > 2 || (precision & ~(0xff | JACPCG_REFINE_FP64)))
+    return fail(JACPCG_E_UNSUPPORTED, "unknown precision 0x%x", precision);
+  rc = check_session(s);
+  if (rc) return rc;
+  if (batch == 0) {
+    if (stats) std::memset(stats, 0, sizeof *stats);
+    return JACPCG_OK;
+  }
+  JP_HIP(hipSetDevice(s->device));
+  return s->run_block((hipStream_t)stream, batch, M1, Mc, M2, K1, K2, (const float2*)H, ldh, stride_h, xi, power,
+                      tol, max_iter, gram_prec, refine, (flags & JACPCG_PRECOND_NONE) != 0,
+                      (flags & JACPCG_EPILOGUE_FP32) == 0, refine_tol, (float2*)G, ldg, stride_g, stats);
+}
+
 int rzf_sinr(jacpcg_session* s, void* stream, int batch, int M, int K, const jacpcg_c64* H, int64_t ldh,
              int64_t stride_h, const jacpcg_c64* W, int64_t ldw, int64_t stride_w, double sigma2, float* sinr,
              float* se) {

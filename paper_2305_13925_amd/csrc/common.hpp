@@ -141,6 +141,8 @@ hipError_t launch_gram64(const Gram64Launch& g, hipStream_t s);
 hipError_t launch_residual(const ResidualLaunch& r, hipStream_t s);
 hipError_t launch_accumulate(const AccumulateLaunch& a, hipStream_t s);
 int residual_workgroups_per_instance(int nrhs);
+hipError_t launch_zero_block(float2* G, int64_t ld, int64_t stride, int batch, int row0, int nrows, int col0,
+                             int ncols, hipStream_t s);
 hipError_t launch_fill_synthetic(float2* H, size_t n, uint32_t seed, hipStream_t s);
 hipError_t launch_eval(const EvalLaunch& e, hipStream_t s);
 hipError_t launch_widen(const float2* X, int64_t ldx, int64_t stride_x, int batch, int K, int n,

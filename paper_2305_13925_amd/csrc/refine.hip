@@ -261,7 +261,28 @@ __global__ void fill_synthetic_kernel(float2* __restrict__ H, size_t n, uint32_t
   H[i] = make_float2(a, b);
 }
 
+// Zero rows [row0, row0 + nrows) x columns [col0, col0 + ncols) of a batch of
+// column-major matrices (ld, stride): the zero blocks of a block precoder.
+__global__ void zero_block_kernel(float2* __restrict__ G, int64_t ld, int64_t stride, int row0, int nrows, int col0,
+                                  int ncols, int64_t total) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const int64_t per = (int64_t)nrows * ncols;
+  const int64_t b = i / per, e = i - b * per;
+  const int c = (int)(e / nrows), r = (int)(e - (int64_t)c * nrows);
+  G[b * stride + (int64_t)(col0 + c) * ld + row0 + r] = make_float2(0.f, 0.f);
+}
+
 }  // namespace
+
+hipError_t launch_zero_block(float2* G, int64_t ld, int64_t stride, int batch, int row0, int nrows, int col0,
+                             int ncols, hipStream_t s) {
+  const int64_t total = (int64_t)batch * nrows * ncols;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(zero_block_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, G, ld, stride, row0,
+                     nrows, col0, ncols, total);
+  return hipGetLastError();
+}
 
 hipError_t launch_fill_synthetic(float2* H, size_t n, uint32_t seed, hipStream_t s) {
   if (n == 0) return hipSuccess;

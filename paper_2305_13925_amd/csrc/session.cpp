@@ -412,6 +412,53 @@ int jacpcg_session::run_rzf(hipStream_t st, int batch, int M, int K, const float
 }
 
 // ---------------------------------------------------------------------------
+// Subarray-block RZF: three independent batched precoders on strided views.
+// ---------------------------------------------------------------------------
+int jacpcg_session::run_block(hipStream_t st, int batch, int M1, int Mc, int M2, int K1, int K2, const float2* H,
+                              int64_t ldh, int64_t stride_h, double xi, double power, double tol, int max_iter,
+                              int gram_prec, bool refine, bool precond_none, bool split_epilogue, double refine_tol,
+                              float2* G, int64_t ldg, int64_t stride_g, jacpcg_stats* stats) {
+  const int M = M1 + Mc + M2, K = K1 + K2;
+  // The blocks outside the groups' subarrays are zero (eq. 6).
+  S_HIP(launch_zero_block(G, ldg, stride_g, batch, 0, M1, K1, K2, st));
+  S_HIP(launch_zero_block(G, ldg, stride_g, batch, M1 + Mc, M2, 0, K1, st));
+  struct Block {
+    int row0, rows, col0, cols;
+  };
+  const Block blocks[3] = {{0, M1, 0, K1}, {M1, Mc, 0, K}, {M1 + Mc, M2, K1, K2}};
+  jacpcg_stats acc{};
+  bool first = true;
+  int worst = JACPCG_OK;
+  for (const Block& bl : blocks) {
+    if (bl.rows == 0 || bl.cols == 0) continue;
+    jacpcg_stats part{};
+    const int rc = run_rzf(st, batch, bl.rows, bl.cols, H + bl.row0 + (int64_t)bl.col0 * ldh, ldh, stride_h,
+                           bl.cols, nullptr, 0, 0, xi, power, tol, max_iter, gram_prec, refine, precond_none,
+                           split_epilogue, refine_tol, G + bl.row0 + (int64_t)bl.col0 * ldg, ldg, stride_g, nullptr,
+                           nullptr, stats ? &part : nullptr);
+    if (rc < 0) return rc;
+    if (!stats) continue;
+    if (first) {
+      acc = part;
+      first = false;
+    } else {
+      acc.max_rel_residual = std::max(acc.max_rel_residual, part.max_rel_residual);
+      acc.max_refine_residual = std::max(acc.max_refine_residual, part.max_refine_residual);
+      acc.max_iters = std::max(acc.max_iters, part.max_iters);
+      acc.refine_steps = std::max(acc.refine_steps, part.refine_steps);
+      acc.beta_pow_min = std::min(acc.beta_pow_min, part.beta_pow_min);
+      acc.beta_pow_max = std::max(acc.beta_pow_max, part.beta_pow_max);
+    }
+    if (part.worst_status < 0 || (worst >= 0 && part.worst_status > worst)) worst = part.worst_status;
+  }
+  (void)M;
+  if (!stats) return JACPCG_OK;
+  acc.worst_status = worst;
+  *stats = acc;
+  return worst;
+}
+
+// ---------------------------------------------------------------------------
 // Precoder evaluation: C = H^H W, per-user SINR and sum rate.
 // ---------------------------------------------------------------------------
 int jacpcg_session::run_sinr(hipStream_t st, int batch, int M, int K, const float2* H, int64_t ldh,

@@ -151,6 +151,25 @@ def test_sinr_validation(kw, word):
     assert word in _err()
 
 
+def _blk(**kw):
+    a = dict(batch=2, M1=8, Mc=4, M2=8, K1=2, K2=3, H=FAKE, ldh=20, sh=100, xi=0.5, power=1.0, tol=0.0, it=4, prec=0,
+             flags=0, rtol=1e-10, G=FAKE, ldg=20, sg=100)
+    a.update(kw)
+    return L.rzf_block_precoder(NULL, NULL, a["batch"], a["M1"], a["Mc"], a["M2"], a["K1"], a["K2"], a["H"],
+                                a["ldh"], a["sh"], a["xi"], a["power"], a["tol"], a["it"], a["prec"], a["flags"],
+                                a["rtol"], a["G"], a["ldg"], a["sg"], NULL)
+
+
+@pytest.mark.parametrize("kw,word", [
+    (dict(M1=-1), "subarray"), (dict(K2=-1), "group"), (dict(ldg=19), "ldg"), (dict(sg=99), "stride_g"),
+    (dict(G=NULL), "G"), (dict(ldh=19), "ldh"), (dict(K1=200, K2=100, sh=6000, sg=6000), "K"),
+    (dict(M1=0, Mc=0, M2=0), "M"), (dict(power=-1.0), "power"),
+])
+def test_block_validation(kw, word):
+    assert _blk(**kw) == bd.E_INVALID_ARG
+    assert word in _err()
+
+
 def test_plain_validation():
     rc = L.rzf_precoder_plain(NULL, NULL, 1, 32, 300, FAKE, 32, 0, 0.5, 1.0, 0.0, 4, 0, FAKE, 32, 0, NULL, NULL)
     assert rc == bd.E_INVALID_ARG and "K" in _err()
