@@ -46,6 +46,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=3.0,
                     help="measured seconds of the Poisson serving stream (0: skip)")
+    ap.add_argument("--no-rows", action="store_true", help="skip the adjacent rows (transmit, block, SINR)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for the HBM traffic counters)")
     return ap.parse_args()
@@ -154,6 +155,66 @@ def cpu_best(H_host, xi, n=64):
             out[label] = round(n * reps / (time.perf_counter() - t0), 1)
     out.update(unit="precoders/s", threads=int(threads), kind="numpy complex64 direct (batched LU solve)",
                sample=f"{n} instances")
+    return out
+
+
+def next_rows(bd, torch, sess, H, xi, stream, reps=20):
+    """Throughput of the adjacent rows on the headline channels: per-symbol
+    transmission (one symbol vector per instance), the subarray-block
+    precoder, the SINR / sum-rate evaluator, and Jacobi-PCG vs plain CG
+    iteration counts."""
+    batch, K, M = H.shape
+    out = {}
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    g = torch.Generator(device="cuda").manual_seed(1)
+    S = (torch.randint(0, 2, (batch, 1, K), generator=g, device="cuda") * 2 - 1).to(torch.complex64)
+    x = torch.empty((batch, 1, M), dtype=torch.complex64, device="cuda")
+    ms = timed(lambda: bd.rzf_transmit(sess, H, S, xi, max_iter=8, precision=bd.GRAM_BF16X6, x=x, stream=stream))
+    # HBM: the Gram and the epilogue each read H; x is M x 1 per instance
+    out["transmit_nsym1"] = {"ms": round(ms, 4), "symbol_vectors_per_s": round(batch / (ms / 1e3), 1),
+                             "hbm_GBs": round(batch * (16.0 * M * K + 8.0 * M) / (ms / 1e3) / 1e9, 1),
+                             "config": f"{batch} x (M={M}, K={K}), one QPSK vector each, T=8, split-BF16 Gram"}
+    M1, Mc, M2, K1 = 3 * M // 8, M // 4, 3 * M // 8, K // 2
+    G = torch.empty_like(H)
+    ms = timed(lambda: bd.rzf_block_precoder(sess, H, xi, M1, Mc, M2, K1, K - K1, max_iter=8,
+                                             precision=bd.GRAM_BF16X6, G=G, stream=stream))
+    out["block_precoder"] = {"ms": round(ms, 4), "precoders_per_s": round(batch / (ms / 1e3), 1),
+                             "config": f"{batch} x (M1={M1}, Mc={Mc}, M2={M2}, K1={K1}, K2={K - K1}), T=8"}
+    W = bd.rzf_precoder(sess, H, xi, max_iter=8, stream=stream)
+    sinr = torch.empty((batch, K), dtype=torch.float32, device="cuda")
+    se = torch.empty((batch,), dtype=torch.float32, device="cuda")
+    ms = timed(lambda: bd.rzf_sinr(sess, H, W, 0.1, sinr=sinr, se=se, stream=stream))
+    t_hbm = batch * 16.0 * M * K / (PEAK_HBM_GBS * 1e9)
+    t_mma = batch * 8.0 * M * K * (-(-K // 32) * 32) / (PEAK_FP32_MFMA_TFLOPS * 1e12)
+    out["sinr"] = {"ms": round(ms, 4), "instances_per_s": round(batch / (ms / 1e3), 1),
+                   "bound": "hbm" if t_hbm >= t_mma else "mfma",
+                   "frac_of_roof": round(max(t_hbm, t_mma) / (ms / 1e3), 4)}
+    # Jacobi-PCG vs plain CG on the gain-normalised channels at 20 dB, where
+    # the users' gains (the diagonal of A) spread and the systems are not ~xi I
+    from channelgen import channel_batch, workload
+    n = 64
+    Hn = torch.from_numpy(channel_batch(workload("batched", gain="normalised"), n=n)).to("cuda")
+    A = bd.jacpcg_gram(sess, Hn, K / 100.0)
+    counts = {}
+    for name, fl in (("jacobi", bd.PRECOND_JACOBI), ("cg", bd.PRECOND_NONE)):
+        it = torch.zeros((n, 1), dtype=torch.int32, device="cuda")
+        bd.jacpcg_solve(sess, A, S[:n].contiguous(), tol=1e-6, max_iter=512, flags=fl, iters=it, stream=stream)
+        torch.cuda.synchronize()
+        c = it.cpu().numpy()[:, 0]
+        counts[name] = {"mean": round(float(c.mean()), 2), "max": int(c.max())}
+    out["iterations_to_1e-6"] = dict(counts, instances=n, rhs="one QPSK vector",
+                                     channels="batched workload, gain-normalised, 20 dB (xi = K/100)")
     return out
 
 
@@ -287,6 +348,8 @@ def main():
         cpu, err_T, err_64 = cpu_baseline(H_host, xi, T, W.cpu().numpy(), a.cpu_seconds)
         best = cpu_best(H_host, xi)
 
+    rows = next_rows(bd, torch, sess, H, xi, stream) if not a.no_rows else None
+
     serving = None
     if a.serve_seconds > 0:
         from paper_2305_13925_amd.serve import run_serving
@@ -327,6 +390,7 @@ def main():
         "cpu_baseline": cpu,
         "cpu_best": best,
         "serving": serving,
+        "rows": rows,
     }
     print(json.dumps(out), flush=True)
     sess.close()
