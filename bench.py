@@ -200,6 +200,33 @@ def next_rows(bd, torch, sess, H, xi, stream, reps=20):
     out["sinr"] = {"ms": round(ms, 4), "instances_per_s": round(batch / (ms / 1e3), 1),
                    "bound": "hbm" if t_hbm >= t_mma else "mfma",
                    "frac_of_roof": round(max(t_hbm, t_mma) / (ms / 1e3), 4)}
+    # Visibility-region sparsity: the stress workload (64 x M=8192, K=256,
+    # regions of 1-3 of 32 subarrays, xi = 1e-3) with users in region order,
+    # dense path against the span-restricted Gram and tile-skipping solver
+    from channelgen import sorted_channel_batch, workload as wl
+    ws = wl("stress")
+    Hs_np, spans_np = sorted_channel_batch(ws)
+    Hs = torch.from_numpy(Hs_np).to("cuda")
+    spans = torch.from_numpy(spans_np).to("cuda")
+    Ws = torch.empty_like(Hs)
+    vr = {}
+    for name, fn in (("dense", lambda: bd.rzf_precoder(sess, Hs, ws.xi, tol=1e-6, max_iter=1024, W=Ws,
+                                                       stream=stream)),
+                     ("vr", lambda: bd.rzf_precoder_vr(sess, Hs, ws.xi, user_span=spans, tol=1e-6, max_iter=1024,
+                                                       W=Ws, stream=stream))):
+        fn()
+        sess.phase_times(reset=True)
+        sess.set_profiling(True)
+        ms_v = timed(fn)
+        sess.set_profiling(False)
+        ph = sess.phase_times(reset=True)
+        vr[name] = {"ms": round(ms_v, 3),
+                    "phases_us": {k: round(v[0] / v[1] * 1e3, 1) for k, v in ph.items() if v[1]}}
+    vr["speedup"] = round(vr["dense"]["ms"] / vr["vr"]["ms"], 2)
+    vr["config"] = "stress: 64 x (M=8192, K=256), r=0.95, regions of 1-3 of 32 subarrays, xi=1e-3, users in region order, FP32 Gram, tol 1e-6"
+    out["vr_sparse"] = vr
+    del Hs, Ws
+
     # Jacobi-PCG vs plain CG on the gain-normalised channels at 20 dB, where
     # the users' gains (the diagonal of A) spread and the systems are not ~xi I
     from channelgen import channel_batch, workload

@@ -18,4 +18,7 @@ from .xlmimo import (  # noqa: F401
     device_pool,
     block_channel_instance,
     block_channel_batch,
+    vr_order,
+    vr_spans,
+    sorted_channel_batch,
 )

@@ -131,6 +131,36 @@ def channel_instance(M, S, K, r, vr, seed, index, gain="literal"):
     return h.astype(np.complex64), meta
 
 
+def vr_order(meta):
+    """User order by visibility region (start subarray, then length): a
+    permutation under which A = H^H H + xi I is banded, since users with
+    disjoint regions have A_ij = 0 (eq. 4, D_k binary)."""
+    return np.lexsort((meta["vr_len"], meta["vr_start"]))
+
+
+def vr_spans(meta, M, S):
+    """Per-user antenna span [first, end) of the visibility region: int32 [K, 2]."""
+    Ms = M // S
+    first = meta["vr_start"] * Ms
+    return np.stack([first, first + meta["vr_len"] * Ms], axis=1).astype(np.int32)
+
+
+def sorted_channel_batch(w: Workload, n=None, start=0, seed=None, gain=None):
+    """Instances of workload w with each instance's users put in VR order.
+    Returns (complex64 [n, K, M], int32 spans [n, K, 2])."""
+    n = w.batch if n is None else int(n)
+    seed = w.seed if seed is None else seed
+    gain = w.gain if gain is None else gain
+    H = np.empty((n, w.K, w.M), dtype=np.complex64)
+    spans = np.empty((n, w.K, 2), dtype=np.int32)
+    for b in range(n):
+        h, meta = channel_instance(w.M, w.S, w.K, w.r, w.vr, seed, start + b, gain)
+        order = vr_order(meta)
+        H[b] = h[order]
+        spans[b] = vr_spans(meta, w.M, w.S)[order]
+    return H, spans
+
+
 def channel_batch(w: Workload, n=None, start=0, seed=None, gain=None):
     """Instances start .. start+n-1 of workload w as complex64 [n, K, M]."""
     n = w.batch if n is None else int(n)

@@ -220,6 +220,27 @@ int rzf_precoder_plain(jacpcg_session* s, void* stream, int batch, int M, int K,
                        jacpcg_c64* W, int64_t ldw, int64_t stride_w,
                        jacpcg_c64* X_out, jacpcg_stats* stats);
 
+/* rzf_precoder exploiting visibility-region sparsity (Sec. II, eq. 4; the
+ * sparsity of P_i noted in Sec. III): user k's channel is zero outside the
+ * antenna span [user_span[2k], user_span[2k+1]) of its visibility region, so
+ * A_ij = 0 when the spans of users i and j do not overlap. Per 32-user block
+ * the hull of its users' spans is formed; each Gram tile contracts only the
+ * antennas where its two blocks overlap, and the solver skips the tiles of A
+ * whose blocks do not overlap (exact zeros). The skipped terms are exact
+ * zeros, so the result is rzf_precoder's up to the summation order.
+ * Effective for K > 64 (smaller K runs the dense kernels); most effective
+ * with users ordered by the position of their region (A then has a band of
+ * nonzero tiles).
+ * user_span: device int32, batch x K x 2 (first, end) per user, or NULL to
+ *   find each user's first and last nonzero antenna on the device (one read of
+ *   H). Channel entries outside a given span are treated as zero.
+ * Every other argument as rzf_precoder (X64_out not available). */
+int rzf_precoder_vr(jacpcg_session* s, void* stream, int batch, int M, int K,
+                    const jacpcg_c64* H, int64_t ldh, int64_t stride_h, const int32_t* user_span,
+                    double xi, double power, double tol, int max_iter, int precision, int flags,
+                    double refine_tol, jacpcg_c64* W, int64_t ldw, int64_t stride_w,
+                    jacpcg_c64* X_out, jacpcg_stats* stats);
+
 /* Per-symbol transmission (eqs. 15-16): for each instance and each of its
  * nsym symbol vectors s (K x 1), w = A^{-1} s by Jacobi-PCG (or plain CG with
  * JACPCG_PRECOND_NONE) on A = H^H H + xi I, and the transmitted vector

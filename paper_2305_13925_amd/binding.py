@@ -112,6 +112,9 @@ def _declare(lib):
     lib.rzf_transmit.argtypes = [_vp, _vp, C.c_int, C.c_int, C.c_int, C.c_int, _vp, C.c_int64, C.c_int64, _vp,
                                  C.c_int64, C.c_int64, C.c_double, C.c_double, C.c_double, C.c_int, C.c_int, C.c_int,
                                  _vp, C.c_int64, C.c_int64, _vp, C.POINTER(JacpcgStats)]
+    lib.rzf_precoder_vr.argtypes = [_vp, _vp, C.c_int, C.c_int, C.c_int, _vp, C.c_int64, C.c_int64, _vp, C.c_double,
+                                    C.c_double, C.c_double, C.c_int, C.c_int, C.c_int, C.c_double, _vp, C.c_int64,
+                                    C.c_int64, _vp, C.POINTER(JacpcgStats)]
     lib.rzf_block_precoder.argtypes = [_vp, _vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, _vp,
                                        C.c_int64, C.c_int64, C.c_double, C.c_double, C.c_double, C.c_int, C.c_int,
                                        C.c_int, C.c_double, _vp, C.c_int64, C.c_int64, C.POINTER(JacpcgStats)]
@@ -127,7 +130,8 @@ def _declare(lib):
     lib.jacpcg_session_clock_us.restype = C.c_double
     for name in ("jacpcg_session_create", "jacpcg_session_set_profiling", "jacpcg_session_phase_times",
                  "jacpcg_gram", "jacpcg_solve", "rzf_precoder", "rzf_precoder_plain", "rzf_transmit", "rzf_sinr",
-                 "rzf_block_precoder", "jacpcg_submit", "jacpcg_session_set_graphs", "jacpcg_autotune",
+                 "rzf_block_precoder", "rzf_precoder_vr", "jacpcg_submit", "jacpcg_session_set_graphs",
+                 "jacpcg_autotune",
                  "jacpcg_poll", "jacpcg_wait", "jacpcg_cancel"):
         getattr(lib, name).restype = C.c_int
     return lib
@@ -355,6 +359,31 @@ def rzf_transmit(session, H, S, xi, power=1.0, tol=0.0, max_iter=16, precision=G
     if stats:
         return x, st.as_dict(), rc
     return x
+
+
+def rzf_precoder_vr(session, H, xi, user_span=None, power=1.0, tol=0.0, max_iter=16, precision=GRAM_FP32,
+                    flags=PRECOND_JACOBI, refine_tol=1e-10, W=None, X_out=None, stats=False, stream=None):
+    """rzf_precoder exploiting visibility-region sparsity. user_span: int32
+    [batch, K, 2] device tensor of per-user antenna spans (first, end), or
+    None to find them on the device."""
+    torch = _torch()
+    _require(H, "H", torch.complex64)
+    batch, K, M = H.shape
+    if user_span is not None:
+        _require(user_span, "user_span", torch.int32, (batch, K, 2))
+    if W is None:
+        W = torch.empty((batch, K, M), dtype=torch.complex64, device=H.device)
+    _require(W, "W", torch.complex64, (batch, K, M))
+    if X_out is not None:
+        _require(X_out, "X_out", torch.complex64, (batch, K, K))
+    st = JacpcgStats() if stats else None
+    rc = _check(lib().rzf_precoder_vr(session.handle, _stream(stream), batch, M, K, _ptr(H), M, K * M,
+                                      _ptr(user_span), float(xi), float(power), float(tol), int(max_iter),
+                                      int(precision), int(flags), float(refine_tol), _ptr(W), M, K * M, _ptr(X_out),
+                                      C.byref(st) if st is not None else None))
+    if stats:
+        return W, st.as_dict(), rc
+    return W
 
 
 def rzf_block_precoder(session, H, xi, M1, Mc, M2, K1, K2, power=1.0, tol=0.0, max_iter=16, precision=GRAM_FP32,

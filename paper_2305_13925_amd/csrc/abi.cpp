@@ -304,6 +304,37 @@ int rzf_precoder(jacpcg_session* s, void* stream, int batch, int M, int K, const
                     refine_tol, (float2*)W, ldw, stride_w, (float2*)X_out, (double2*)X64_out, stats);
 }
 
+int rzf_precoder_vr(jacpcg_session* s, void* stream, int batch, int M, int K, const jacpcg_c64* H, int64_t ldh,
+                    int64_t stride_h, const int32_t* user_span, double xi, double power, double tol, int max_iter,
+                    int precision, int flags, double refine_tol, jacpcg_c64* W, int64_t ldw, int64_t stride_w,
+                    jacpcg_c64* X_out, jacpcg_stats* stats) {
+  int rc = check_gram_args(batch, M, K, H, ldh, stride_h, xi, nullptr, 0, 0);
+  if (rc) return rc;
+  JP_CHECK(std::isfinite(power) && power > 0.0, "power must be finite and > 0 (got %g)", power);
+  JP_CHECK(std::isfinite(tol) && tol >= 0.0, "tol must be finite and >= 0 (got %g)", tol);
+  JP_CHECK(max_iter >= 0, "max_iter must be >= 0 (got %d)", max_iter);
+  JP_CHECK((flags & ~(JACPCG_PRECOND_NONE | JACPCG_EPILOGUE_FP32)) == 0, "unknown flags 0x%x", flags);
+  JP_CHECK(std::isfinite(refine_tol) && refine_tol >= 0.0, "refine_tol must be finite and >= 0");
+  JP_CHECK(ldw >= M, "ldw must be >= M (got %lld < %d)", (long long)ldw, M);
+  if (batch > 1) JP_CHECK(stride_w >= ldw * K, "stride_w must be >= ldw * K");
+  if (batch > 0) JP_CHECK(W != nullptr, "W is NULL");
+  const int gram_prec = precision & 0xff;
+  const bool refine = (precision & JACPCG_REFINE_FP64) != 0;
+  if (gram_prec > 2 || (precision & ~(0xff | JACPCG_REFINE_FP64)))
+    return fail(JACPCG_E_UNSUPPORTED, "unknown precision 0x%x", precision);
+  rc = check_session(s);
+  if (rc) return rc;
+  if (batch == 0) {
+    if (stats) std::memset(stats, 0, sizeof *stats);
+    return JACPCG_OK;
+  }
+  JP_HIP(hipSetDevice(s->device));
+  return s->run_rzf((hipStream_t)stream, batch, M, K, (const float2*)H, ldh, stride_h, K, nullptr, 0, 0, xi, power,
+                    tol, max_iter, gram_prec, refine, (flags & JACPCG_PRECOND_NONE) != 0,
+                    (flags & JACPCG_EPILOGUE_FP32) == 0, refine_tol, (float2*)W, ldw, stride_w, (float2*)X_out,
+                    nullptr, stats, true, user_span);
+}
+
 int rzf_transmit(jacpcg_session* s, void* stream, int batch, int M, int K, int nsym, const jacpcg_c64* H,
                  int64_t ldh, int64_t stride_h, const jacpcg_c64* S, int64_t lds, int64_t stride_s, double xi,
                  double power, double tol, int max_iter, int precision, int flags, jacpcg_c64* x, int64_t ldx,

@@ -49,6 +49,8 @@ struct GramLaunch {
   int precision;    // 0 fp32, 1 bf16x3, 2 bf16x6
   int m_split;      // waves per workgroup that split the antenna range (tuned)
   int no_vec;       // 1: some channel pointer or ldh does not allow 16-byte loads
+  const int2* tile_span;  // nullable: per (instance, 32-user block) antenna span [x, y) outside which
+                          // every user of the block has a zero channel; tiles use only the overlap
 };
 
 // Per-workgroup resumable PCG state for chunked launches.
@@ -73,6 +75,8 @@ struct PcgLaunch {
   PcgState st;                              // chunked mode when st.vec != NULL
   int chunk;                                // iterations in this launch (chunked mode)
   int first;                                // chunked mode: 1 on the first launch
+  const int2* tile_span;                    // nullable: user-block antenna spans (as GramLaunch); tiles of A
+                                            // whose blocks' spans are disjoint are zero and skipped (K > 64)
 };
 
 struct PrecoderLaunch {
@@ -118,6 +122,15 @@ struct AccumulateLaunch {
   float2* X32;                              // nullable: rounded copy of the result
 };
 
+// Visibility-region spans: per user the antenna range [first, end) outside
+// which its channel is zero, and per 32-user block the hull of its users'.
+struct SpanLaunch {
+  const float2* H; int64_t ldh, stride_h;   // scanned when user_span_in is NULL
+  const int32_t* user_span_in;              // nullable: batch x K x 2 (first, end) given by the caller
+  int batch, M, K;
+  int2* tile_span;                          // batch x ceil(K/32)
+};
+
 // Precoder evaluation (eqs. 8-10): C = H^H W, per-user SINR, sum rate.
 struct EvalLaunch {
   const float2* H; int64_t ldh, stride_h;
@@ -145,6 +158,7 @@ hipError_t launch_zero_block(float2* G, int64_t ld, int64_t stride, int batch, i
                              int ncols, hipStream_t s);
 hipError_t launch_fill_synthetic(float2* H, size_t n, uint32_t seed, hipStream_t s);
 hipError_t launch_eval(const EvalLaunch& e, hipStream_t s);
+hipError_t launch_spans(const SpanLaunch& sl, hipStream_t s);
 hipError_t launch_widen(const float2* X, int64_t ldx, int64_t stride_x, int batch, int K, int n,
                         double2* out, hipStream_t s);
 

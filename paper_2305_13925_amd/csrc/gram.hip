@@ -65,6 +65,35 @@ __device__ __forceinline__ void panel_tiles(int p, int nt, int& ti, int& tj0, in
   ntj = min(2, nt - tj0);
 }
 
+// Antenna range of a tile (or a panel of tiles) of an instance. Without spans
+// it is [0, M). With visibility-region spans it is the overlap of the row
+// block's span with the column blocks' spans, widened to multiples of `align`
+// (antennas outside a user's span hold zeros, so a wider range changes
+// nothing); an empty overlap gives an empty range (the tile is zero).
+__device__ __forceinline__ void tile_range(const GramLaunch& g, int b, int ti, int tj0, int ntj, int align, int& mb,
+                                           int& me) {
+  mb = 0;
+  me = g.M;
+  if (!g.tile_span) return;
+  const int nt = (g.K + 31) >> 5;
+  const int2 si = g.tile_span[(int64_t)b * nt + ti];
+  int lo = g.M, hi = 0;
+  for (int t = 0; t < ntj; ++t) {
+    const int2 sj = g.tile_span[(int64_t)b * nt + tj0 + t];
+    const int l = max(si.x, sj.x), h = min(si.y, sj.y);
+    if (h > l) {
+      lo = min(lo, l);
+      hi = max(hi, h);
+    }
+  }
+  if (hi <= lo) {
+    mb = me = 0;
+    return;
+  }
+  mb = (lo / align) * align;
+  me = min(g.M, ((hi + align - 1) / align) * align);
+}
+
 // 4 consecutive complex entries row[m .. m+3] as 8 floats (re, im, ...), zero
 // past `mend` or for a padding row.
 template <bool VEC>
@@ -158,9 +187,11 @@ __global__ __launch_bounds__(512) void gram_f32_kernel(GramLaunch g) {
   gptr<const float2> hj = Hb + (int64_t)(vj ? uj : 0) * g.ldh;
   const bool same = (ti == tj);
 
-  const int chunk = ((g.M + nw * 8 - 1) / (nw * 8)) * 8;
-  const int m0 = wave * chunk;
-  const int m1 = min(g.M, m0 + chunk);
+  int mb, me;
+  tile_range(g, b, ti, tj, 1, 8, mb, me);
+  const int chunk = ((me - mb + nw * 8 - 1) / (nw * 8)) * 8;
+  const int m0 = mb + wave * chunk;
+  const int m1 = min(me, m0 + chunk);
 
   floatx16 accR = zero16(), accI = zero16();
   for (int m = m0; m < m1; m += 8) {
@@ -223,9 +254,11 @@ __global__ __launch_bounds__(256) void gram_bf16_kernel(GramLaunch g) {
     hx[q] = Hb + (int64_t)(vx[q] ? ux : 0) * g.ldh;
   }
 
-  const int chunk = ((g.M + nw * 16 - 1) / (nw * 16)) * 16;
-  const int m0 = wave * chunk;
-  const int m1 = min(g.M, m0 + chunk);
+  int mb, me;
+  tile_range(g, b, ti, tj0, ntj, 16, mb, me);
+  const int chunk = ((me - mb + nw * 16 - 1) / (nw * 16)) * 16;
+  const int m0 = mb + wave * chunk;
+  const int m1 = min(me, m0 + chunk);
 
   floatx16 accR[2], accI[2];
 #pragma unroll

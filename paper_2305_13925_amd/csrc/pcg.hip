@@ -94,10 +94,43 @@ __device__ __forceinline__ void apply_a(floatx16& qr, floatx16& qi, const float*
   }
 }
 
+// Visibility-region sparse variant (K > 64, A streamed from L2): the two k
+// slots of one MFMA carry the adjacent columns k = 2s and 2s + 1, so the 16
+// steps of a 32-column block of A stay inside that block, and blocks that are
+// structurally zero for this wave's rows (bit c of `mask` clear: the users'
+// visibility regions do not overlap, so A is exactly zero there) are skipped.
+template <int KT>
+__device__ __forceinline__ void apply_a_vr(floatx16& qr, floatx16& qi, const float2* __restrict__ arow, bool rowvalid,
+                                           int K, int ia, bool zero_diag, unsigned mask, const float2 (*Psh)[32],
+                                           int half, int jl) {
+  qr = zero16();
+  qi = zero16();
+  for (int c = 0; c < KT; ++c) {
+    if (!((mask >> c) & 1u)) continue;  // wave-uniform
+    for (int s0 = 16 * c; s0 < 16 * c + 16; s0 += 8) {
+      float2 av[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int k = 2 * (s0 + e) + half;
+        av[e] = (rowvalid && k < K && !(zero_diag && k == ia)) ? arow[k] : make_float2(0.f, 0.f);
+      }
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const float2 pv = Psh[2 * (s0 + e) + half][jl];
+        qr = mfma32(av[e].x, pv.x, qr);
+        qr = mfma32(av[e].y, -pv.y, qr);
+        qi = mfma32(av[e].x, pv.y, qi);
+        qi = mfma32(av[e].y, pv.x, qi);
+      }
+    }
+  }
+}
+
 // Two waves per SIMD (the register budget of 256 per lane) let one workgroup's
 // reductions overlap another's products.
-template <int KT, bool AREG>
+template <int KT, bool AREG, bool VRS>
 __global__ __launch_bounds__(KT * 64) __attribute__((amdgpu_waves_per_eu(2))) void pcg_f32_kernel(PcgLaunch p) {
+  static_assert(!(VRS && AREG), "the sparse variant streams A");
   constexpr int KP = KT * 32;
   constexpr int KH = KT * 16;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -122,6 +155,18 @@ __global__ __launch_bounds__(KT * 64) __attribute__((amdgpu_waves_per_eu(2))) vo
   const int klim = (ia < K) ? max(0, min(KH, K - half * KH)) : 0;
   const float2* arow = Ab + (int64_t)(ia < K ? ia : 0) * p.lda + half * KH;
   const int diag_s = ia - half * KH;  // step holding A[ia][ia] in this lane, if in [0, KH)
+  // Sparse variant: the 32-column blocks of A that can hold nonzeros in this
+  // wave's rows (spans overlap; the diagonal block always, for xi).
+  unsigned vr_mask = 0;
+  if constexpr (VRS) {
+    const int2 sw = p.tile_span[(int64_t)b * KT + w];
+    for (int c = 0; c < KT; ++c) {
+      const int2 sc = p.tile_span[(int64_t)b * KT + c];
+      if (c == w || min(sw.y, sc.y) > max(sw.x, sc.x)) vr_mask |= 1u << c;
+    }
+    vr_mask = __builtin_amdgcn_readfirstlane(vr_mask);
+  }
+  const float2* arow_full = Ab + (int64_t)(ia < K ? ia : 0) * p.lda;
 
   float ar[AREG ? KH : 1], ai[AREG ? KH : 1];
   if constexpr (AREG) {
@@ -217,7 +262,10 @@ __global__ __launch_bounds__(KT * 64) __attribute__((amdgpu_waves_per_eu(2))) vo
     ++t;
     __syncthreads();  // P visible to all waves
     floatx16 qr, qi;
-    apply_a<KT, AREG>(qr, qi, ar, ai, arow, klim, false, diag_s, Psh, half, jl);
+    if constexpr (VRS)
+      apply_a_vr<KT>(qr, qi, arow_full, ia < K, K, ia, false, vr_mask, Psh, half, jl);
+    else
+      apply_a<KT, AREG>(qr, qi, ar, ai, arow, klim, false, diag_s, Psh, half, jl);
 
     float g[1] = {0.f};
 #pragma unroll
@@ -331,7 +379,10 @@ __global__ __launch_bounds__(KT * 64) __attribute__((amdgpu_waves_per_eu(2))) vo
     for (int r = 0; r < 16; ++r) Psh[w * 32 + d32_row(r, half)][jl] = make_float2(xr[r], xim[r]);
     __syncthreads();
     floatx16 yr, yi;
-    apply_a<KT, AREG>(yr, yi, ar, ai, arow, klim, true, diag_s, Psh, half, jl);
+    if constexpr (VRS)
+      apply_a_vr<KT>(yr, yi, arow_full, ia < K, K, ia, true, vr_mask, Psh, half, jl);
+    else
+      apply_a<KT, AREG>(yr, yi, ar, ai, arow, klim, true, diag_s, Psh, half, jl);
     float q[1] = {0.f};
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
@@ -366,7 +417,13 @@ __global__ void status_reduce_kernel(const int32_t* __restrict__ wg, int ncb, in
 
 template <int KT, bool AREG>
 hipError_t launch_kt(const PcgLaunch& p, int grid, hipStream_t s) {
-  hipLaunchKernelGGL((pcg_f32_kernel<KT, AREG>), dim3(grid), dim3(KT * 64), 0, s, p);
+  if constexpr (!AREG) {
+    if (p.tile_span) {
+      hipLaunchKernelGGL((pcg_f32_kernel<KT, false, true>), dim3(grid), dim3(KT * 64), 0, s, p);
+      return hipGetLastError();
+    }
+  }
+  hipLaunchKernelGGL((pcg_f32_kernel<KT, AREG, false>), dim3(grid), dim3(KT * 64), 0, s, p);
   return hipGetLastError();
 }
 

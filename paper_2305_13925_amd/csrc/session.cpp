@@ -159,7 +159,8 @@ int jacpcg_session::run_rzf(hipStream_t st, int batch, int M, int K, const float
                             int nrhs, const float2* B, int64_t ldb, int64_t stride_b, double xi, double power,
                             double tol, int max_iter, int gram_prec, bool refine, bool precond_none,
                             bool split_epilogue, double refine_tol, float2* W, int64_t ldw, int64_t stride_w,
-                            float2* X_out, double2* X64_out, jacpcg_stats* stats) {
+                            float2* X_out, double2* X64_out, jacpcg_stats* stats, bool vr_sparse,
+                            const int32_t* user_span) {
   // nrhs right-hand-side columns (B = NULL: the identity, nrhs = K).
   const int ncb = (nrhs + 31) / 32;
   const size_t KK = (size_t)K * K;
@@ -184,7 +185,12 @@ int jacpcg_session::run_rzf(hipStream_t st, int batch, int M, int K, const float
   const size_t oRn = refine ? ws.take<double>((size_t)batch * n16) : 0;
   const size_t oQd = refine ? ws.take<double>((size_t)batch * n16) : 0;
   const size_t oWG2 = refine ? ws.take<int32_t>((size_t)batch * ncb) : 0;
+  // visibility-region spans per 32-user block (sparse Gram tiles and solver)
+  const int nt = (K + 31) / 32;
+  const bool use_spans = vr_sparse && nt > 2;
+  const size_t oTS = use_spans ? ws.take<int2>((size_t)batch * nt) : 0;
   if (int rc = reserve(ws)) return rc;
+  const int2* tspan = use_spans ? at<int2>(oTS) : nullptr;
   float2* A = at<float2>(oA);
   float* gdiag = at<float>(oG);
   float2* X = X_out ? X_out : at<float2>(oX);
@@ -200,6 +206,19 @@ int jacpcg_session::run_rzf(hipStream_t st, int batch, int M, int K, const float
     auto run = [&](int phase, auto&& launch) -> hipError_t {
       return timed_run ? timed(q, phase, launch) : launch();
     };
+    if (use_spans) {
+      SpanLaunch sl{};
+      sl.H = H;
+      sl.ldh = ldh;
+      sl.stride_h = stride_h;
+      sl.user_span_in = user_span;
+      sl.batch = batch;
+      sl.M = M;
+      sl.K = K;
+      sl.tile_span = const_cast<int2*>(tspan);
+      hipError_t es = launch_spans(sl, q);
+      if (es != hipSuccess) return es;
+    }
     GramLaunch g{};
     g.H = H;
     g.ldh = ldh;
@@ -215,6 +234,7 @@ int jacpcg_session::run_rzf(hipStream_t st, int batch, int M, int K, const float
     g.gdiag = gdiag;
     g.precision = gram_prec;
     g.m_split = tuner.gram_waves(M, K, gram_prec);
+    g.tile_span = tspan;
     hipError_t e = run(JACPCG_PHASE_GRAM, [&] { return launch_gram(g, q); });
     if (e != hipSuccess) return e;
 
@@ -239,6 +259,7 @@ int jacpcg_session::run_rzf(hipStream_t st, int batch, int M, int K, const float
     p.wg_status = wgs;
     p.gdiag = gdiag;
     p.fpart = fpart;
+    p.tile_span = tspan;
     e = run(JACPCG_PHASE_SOLVE, [&] { return launch_pcg(p, q, nullptr); });
     if (e != hipSuccess) return e;
     e = launch_status_reduce(wgs, ncb, batch, status, q);
@@ -285,7 +306,7 @@ int jacpcg_session::run_rzf(hipStream_t st, int batch, int M, int K, const float
                                     (uint64_t)max_iter, (uint64_t)gram_prec, (uint64_t)precond_none,
                                     (uint64_t)split_epilogue, (uint64_t)(uintptr_t)W, (uint64_t)ldw,
                                     (uint64_t)stride_w, (uint64_t)(uintptr_t)X_out, (uint64_t)(uintptr_t)X64_out,
-                                    (uint64_t)(uintptr_t)arena});
+                                    (uint64_t)(uintptr_t)arena, (uint64_t)vr_sparse, (uint64_t)(uintptr_t)user_span});
     hipGraphExec_t ex = graph_lookup(key);
     if (!ex) {
       hipStream_t cs = capture_stream();
@@ -371,6 +392,7 @@ int jacpcg_session::run_rzf(hipStream_t st, int batch, int M, int K, const float
       pc.max_iter = max_iter;
       pc.precond_none = precond_none;
       pc.wg_status = at<int32_t>(oWG2);
+      pc.tile_span = tspan;
       e = timed(st, JACPCG_PHASE_SOLVE, [&] { return launch_pcg(pc, st, nullptr); });
       if (e != hipSuccess) return hip_error(this, e, "correction pcg launch");
       AccumulateLaunch ac{X64, E32, scale, batch, K, K, 0, X};

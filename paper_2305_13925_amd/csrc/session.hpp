@@ -104,7 +104,8 @@ struct jacpcg_session {
   int run_rzf(hipStream_t st, int batch, int M, int K, const float2* H, int64_t ldh, int64_t stride_h, int nrhs,
               const float2* B, int64_t ldb, int64_t stride_b, double xi, double power, double tol, int max_iter,
               int gram_prec, bool refine, bool precond_none, bool split_epilogue, double refine_tol, float2* W,
-              int64_t ldw, int64_t stride_w, float2* X_out, double2* X64_out, jacpcg_stats* stats);
+              int64_t ldw, int64_t stride_w, float2* X_out, double2* X64_out, jacpcg_stats* stats,
+              bool vr_sparse = false, const int32_t* user_span = nullptr);
   int run_block(hipStream_t st, int batch, int M1, int Mc, int M2, int K1, int K2, const float2* H, int64_t ldh,
                 int64_t stride_h, double xi, double power, double tol, int max_iter, int gram_prec, bool refine,
                 bool precond_none, bool split_epilogue, double refine_tol, float2* G, int64_t ldg, int64_t stride_g,

@@ -137,3 +137,26 @@ def test_inverse_golden():
 def test_cholesky_rejects_non_hpd():
     with pytest.raises(ValueError):
         oracle.chol_inverse(np.array([[1.0, 2.0], [2.0, 1.0]], complex))
+
+
+def test_gram_zero_for_disjoint_visibility_regions():
+    # eq. 4: D_k is binary, so users whose visibility regions share no subarray
+    # have exactly orthogonal channels and A_ij = 0; in VR order A is banded.
+    from channelgen import channel_instance, vr_order, vr_spans
+    h, meta = channel_instance(1024, 32, 48, 0.9, (1, 3), 5, 0)
+    order = vr_order(meta)
+    spans = vr_spans(meta, 1024, 32)[order]
+    A = oracle.gram(h[order].T.astype(np.complex128), 1e-3)
+    disjoint = (np.minimum(spans[:, None, 1], spans[None, :, 1]) <= np.maximum(spans[:, None, 0], spans[None, :, 0]))
+    assert disjoint.any() and np.all(A[disjoint] == 0)
+    assert np.all(np.abs(A[~disjoint & ~np.eye(48, dtype=bool)]) > 0)
+    # H is zero outside each user's span
+    Hs = h[order]
+    for k in range(48):
+        assert np.all(Hs[k, :spans[k, 0]] == 0) and np.all(Hs[k, spans[k, 1]:] == 0)
+    # envelope: in VR order (by start), every user j that starts at or after
+    # user i's region ends is disjoint from i, and those users form a suffix
+    for i in range(48):
+        later = np.flatnonzero(spans[:, 0] >= spans[i, 1])
+        if later.size:
+            assert np.array_equal(later, np.arange(later[0], 48)) and np.all(A[i, later[0]:] == 0)
