@@ -94,6 +94,8 @@ struct PrecoderLaunch {
   int no_vec;                               // 1: some precoder pointer or ldw does not allow 16-byte stores
   int nj;                                   // column tiles per wave: 0 = default rule, 1 or 2 = tuned choice
   int mtiles;                               // split-BF16: 128-antenna blocks per workgroup (0 = default rule)
+  const int2* tile_span;                    // nullable (split-BF16, K > 64): user-block antenna spans; user
+                                            // blocks whose span misses a workgroup's antennas are skipped
 };
 
 struct Gram64Launch {

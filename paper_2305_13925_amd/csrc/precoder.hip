@@ -157,7 +157,25 @@ hipError_t launch_kt(const PrecoderLaunch& e, hipStream_t s) {
 // beta_pow X is split into bf16 parts once per workgroup (Re and Im planes in
 // LDS); H is split on the fly and its negated Im plane is shared by all column
 // tiles, so no other operand shuffling is needed.
-template <int NS, int KT, int NJ, bool FULL>
+// Index of the n-th set bit of a step mask (the last set bit when n is past
+// the end, 0 for an empty mask); wave-uniform arguments, scalar work.
+__device__ __forceinline__ int nth_active(unsigned act, int n) {
+  int last = 0;
+#pragma unroll
+  for (int s = 0; s < 16; ++s) {
+    if ((act >> s) & 1u) {
+      if (n == 0) return s;
+      --n;
+      last = s;
+    }
+  }
+  return last;
+}
+
+// VR: visibility-region sparse variant (one 128-antenna block per workgroup):
+// only the user steps whose 32-user block has a span reaching this block's
+// antennas are computed (the others hold zero channel entries here).
+template <int NS, int KT, int NJ, bool FULL, bool VR>
 __global__ __launch_bounds__(256) void precoder_bf16_kernel(PrecoderLaunch e) {
   constexpr int KP = KT * 32;
   constexpr int K8 = KP / 8;  // groups of 8 users (one lane half of one step)
@@ -188,11 +206,31 @@ __global__ __launch_bounds__(256) void precoder_bf16_kernel(PrecoderLaunch e) {
   // lane's antenna row, users 8 * (2 * step + half) .. +7. Steps past the last
   // block reload the last one, so every load can be issued unconditionally.
   constexpr int S = K8 / 2;
+  static_assert(S <= 16, "step masks hold 16 steps");
+  unsigned act = (S >= 32) ? ~0u : ((1u << S) - 1u);
+  int nact = S;
+  if constexpr (VR) {
+    const int m_lo = blk0 * 128, m_hi = min(e.M, m_lo + 128);
+    act = 0;
+    for (int c = 0; c < KT; ++c) {
+      const int2 sp = e.tile_span[(int64_t)b * KT + c];
+      if (sp.y > m_lo && sp.x < m_hi) act |= 3u << (2 * c);  // steps 2c, 2c+1: users 32c .. 32c+31
+    }
+    act = __builtin_amdgcn_readfirstlane(act);
+    nact = __popc(act);
+  }
   auto issue = [&](int gs, float (&hr)[8], float (&hi)[8]) {
-    int blk = blk0 + gs / S, st = gs % S;
-    if (blk >= blk1) {
-      blk = blk1 - 1;
-      st = S - 1;
+    int blk, st;
+    if constexpr (VR) {
+      blk = blk0;
+      st = nth_active(act, gs);
+    } else {
+      blk = blk0 + gs / S;
+      st = gs % S;
+      if (blk >= blk1) {
+        blk = blk1 - 1;
+        st = S - 1;
+      }
     }
     const int mrow = blk * 128 + w * 32 + jl;
     const bool v = FULL || mrow < e.M;
@@ -218,6 +256,7 @@ __global__ __launch_bounds__(256) void precoder_bf16_kernel(PrecoderLaunch e) {
   gptr<const float2> Xb = as_global(e.X + (int64_t)b * e.stride_x);
   for (int idx = threadIdx.x; idx < K8 * NC; idx += 256) {
     const int jj = idx % NC, k8 = idx / NC;
+    if (VR && !((act >> (k8 >> 1)) & 1u)) continue;  // a user step this block never reads
     const int j = cw * NC + jj;
     float re[8], im[8];
 #pragma unroll
@@ -276,10 +315,18 @@ __global__ __launch_bounds__(256) void precoder_bf16_kernel(PrecoderLaunch e) {
       wr[t] = zero16();
       wi[t] = zero16();
     }
+    if constexpr (VR) {
 #pragma unroll 1
-    for (int st = 0; st < S; st += 2, gs += 2) {
-      compute(hrA, hiA, st, gs + 2);
-      compute(hrB, hiB, st + 1, gs + 3);
+      for (int i = 0; i < nact; i += 2) {
+        compute(hrA, hiA, nth_active(act, i), i + 2);
+        if (i + 1 < nact) compute(hrB, hiB, nth_active(act, i + 1), i + 3);
+      }
+    } else {
+#pragma unroll 1
+      for (int st = 0; st < S; st += 2, gs += 2) {
+        compute(hrA, hiA, st, gs + 2);
+        compute(hrB, hiB, st + 1, gs + 3);
+      }
     }
     const int m = blk * 128 + w * 32 + jl;
     if (FULL || m < e.M) {
@@ -301,17 +348,21 @@ hipError_t launch_bf16_nj(const PrecoderLaunch& e, hipStream_t s) {
   const int nblk = (e.M + 127) / 128;
   PrecoderLaunch p = e;
   // Blocks of 128 antennas per workgroup: enough to amortise the split of X,
-  // few enough to keep several workgroups per compute unit busy.
-  if (p.mtiles <= 0) p.mtiles = nblk >= 8 ? 2 : 1;
+  // few enough to keep several workgroups per compute unit busy. The sparse
+  // variant takes one block per workgroup (its user steps depend on it).
+  const bool vr = e.tile_span != nullptr && KT > 2;
+  if (vr)
+    p.mtiles = 1;
+  else if (p.mtiles <= 0)
+    p.mtiles = nblk >= 8 ? 2 : 1;
   p.mtiles = std::min(p.mtiles, nblk);
   const int nmb = (nblk + p.mtiles - 1) / p.mtiles;
   const size_t lds = (size_t)2 * NS * (KT * 4) * 32 * NJ * 16;
   // FULL: every user, antenna and column of every tile is in range (no masks).
   const bool full = (e.K == KT * 32) && (e.M % 128 == 0) && (e.nrhs % (32 * NJ) == 0);
   const int grid = e.batch * nmb * ((e.nrhs + 32 * NJ - 1) / (32 * NJ));
-  auto kf = precoder_bf16_kernel<NS, KT, NJ, true>;
-  auto km = precoder_bf16_kernel<NS, KT, NJ, false>;
-  auto k = full ? kf : km;
+  auto k = full ? (vr ? precoder_bf16_kernel<NS, KT, NJ, true, true> : precoder_bf16_kernel<NS, KT, NJ, true, false>)
+                : (vr ? precoder_bf16_kernel<NS, KT, NJ, false, true> : precoder_bf16_kernel<NS, KT, NJ, false, false>);
   if (lds > 65536) (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   hipLaunchKernelGGL(k, dim3(grid), dim3(256), lds, s, p);
   return hipGetLastError();

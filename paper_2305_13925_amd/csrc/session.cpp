@@ -290,6 +290,7 @@ int jacpcg_session::run_rzf(hipStream_t st, int batch, int M, int K, const float
     E.nj = tuner.precoder_nj(M, K, E.split);
     E.fpart64 = quad64;  // refined path: ||H X64||^2 from the last FP64 residual
     E.ncb64 = nq;
+    E.tile_span = tspan;
     hipError_t e = timed_run ? timed(q, JACPCG_PHASE_EPILOGUE, [&] { return launch_precoder(E, q); })
                              : launch_precoder(E, q);
     if (e != hipSuccess) return e;
