@@ -267,10 +267,10 @@ int Scheduler::launch(Slot& sl, const std::vector<uint64_t>& members, const std:
   sl.K = K;
   const BatchLayout lay(G, K);
   if (lay.total > sl.ws_bytes) {
+    const size_t want = std::max(lay.total, sl.ws_bytes * 2);  // grow geometrically
     if (sl.ws) (void)hipFree(sl.ws);  // the slot is idle: its previous batch completed
     sl.ws = nullptr;
     sl.ws_bytes = 0;
-    const size_t want = std::max(lay.total, sl.ws_bytes * 2);
     if (hipMalloc((void**)&sl.ws, want) != hipSuccess) {
       (void)hipGetLastError();
       return JACPCG_E_OUT_OF_MEMORY;

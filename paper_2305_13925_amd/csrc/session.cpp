@@ -115,6 +115,7 @@ hipGraphExec_t jacpcg_session::graph_lookup(uint64_t key) {
 void jacpcg_session::graph_insert(uint64_t key, hipGraphExec_t exec) {
   constexpr size_t kMaxGraphs = 32;
   if (graphs.size() >= kMaxGraphs) {
+    (void)hipDeviceSynchronize();  // the evicted graph may still be executing
     (void)hipGraphExecDestroy(graphs.front().exec);
     graphs.erase(graphs.begin());
   }

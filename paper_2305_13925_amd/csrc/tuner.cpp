@@ -9,6 +9,7 @@
 namespace jacpcg {
 
 int Tuner::gram_waves(int M, int K, int precision) const {
+  std::lock_guard<std::mutex> lk(mu_);
   auto it = gram_waves_.find(std::make_tuple(M, K, precision));
   if (it != gram_waves_.end()) return it->second;
   (void)K;
@@ -18,15 +19,20 @@ int Tuner::gram_waves(int M, int K, int precision) const {
 }
 
 void Tuner::set_gram_waves(int M, int K, int precision, int waves) {
+  std::lock_guard<std::mutex> lk(mu_);
   gram_waves_[std::make_tuple(M, K, precision)] = waves;
 }
 
 int Tuner::precoder_nj(int M, int K, int split) const {
+  std::lock_guard<std::mutex> lk(mu_);
   auto it = precoder_nj_.find(std::make_tuple(M, K, split));
   return it != precoder_nj_.end() ? it->second : 0;
 }
 
-void Tuner::set_precoder_nj(int M, int K, int split, int nj) { precoder_nj_[std::make_tuple(M, K, split)] = nj; }
+void Tuner::set_precoder_nj(int M, int K, int split, int nj) {
+  std::lock_guard<std::mutex> lk(mu_);
+  precoder_nj_[std::make_tuple(M, K, split)] = nj;
+}
 
 namespace {
 
@@ -59,6 +65,7 @@ bool Tuner::load(const std::string& path) {
   std::stringstream ss;
   ss << f.rdbuf();
   const std::string s = ss.str();
+  std::lock_guard<std::mutex> lk(mu_);
   parse_list(s, "\"gram_waves\"", [&](const int* v) {
     if (v[3] >= 1 && v[3] <= 8) gram_waves_[std::make_tuple(v[0], v[1], v[2])] = v[3];
   });
@@ -72,6 +79,7 @@ bool Tuner::save(const std::string& path) const {
   if (path.empty()) return false;
   std::ofstream f(path);
   if (!f) return false;
+  std::lock_guard<std::mutex> lk(mu_);
   auto dump = [&](const char* key, const std::map<std::tuple<int, int, int>, int>& m) {
     f << "\"" << key << "\": [";
     bool first = true;
