@@ -129,6 +129,25 @@ def cpu_baseline(H_host, xi, T, W_gpu, budget_s):
         float(np.max(errs_T)), float(np.max(errs_64)) if errs_64 else None
 
 
+def oracle_other_workloads():
+    """The oracle on small subsets of the precision (4 instances) and stress (2
+    instances) workloads, as precoders/s, with the solve settings of those
+    workloads (tolerance 1e-6)."""
+    import oracle
+    from channelgen import channel_batch, workload
+    out = {}
+    for name, n in (("precision", 4), ("stress", 2)):
+        w = workload(name)
+        H = channel_batch(w, n=n)
+        xi = w.xi_values()[0]
+        t0 = time.perf_counter()
+        for b in range(n):
+            oracle.rzf(H[b].T.astype(np.complex128), xi, tol=1e-6, max_iter=w.max_iter)
+        out[name] = {"precoders_per_s": round(n / (time.perf_counter() - t0), 3),
+                     "sample": f"{n} instances of M={w.M}, K={w.K}, tol 1e-6"}
+    return out
+
+
 def cpu_best(H_host, xi, n=64):
     """A vectorised direct CPU path (complex64 batched Gram, LAPACK Cholesky
     solve, power normalisation) on n instances, with all BLAS threads and with
@@ -223,9 +242,44 @@ def next_rows(bd, torch, sess, H, xi, stream, reps=20):
         vr[name] = {"ms": round(ms_v, 3),
                     "phases_us": {k: round(v[0] / v[1] * 1e3, 1) for k, v in ph.items() if v[1]}}
     vr["speedup"] = round(vr["dense"]["ms"] / vr["vr"]["ms"], 2)
+    _, vst, _ = bd.rzf_precoder_vr(sess, Hs, ws.xi, user_span=spans, tol=1e-6, max_iter=1024, W=Ws, stats=True,
+                                   stream=stream)
+    vr["max_iters_to_1e-6"] = vst["max_iters"]
     vr["config"] = "stress: 64 x (M=8192, K=256), r=0.95, regions of 1-3 of 32 subarrays, xi=1e-3, users in region order, FP32 Gram, tol 1e-6"
     out["vr_sparse"] = vr
     del Hs, Ws
+
+    # Precision workload: 256 x (M=4096, K=128), r=0.7, 10 dB, FP32 Gram and
+    # PCG to 1e-6 plus FP64-residual refinement to 1e-10 (channels of the same
+    # law drawn on the device); error of sampled results against the FP64
+    # direct precoder (oracle, CPU)
+    import oracle
+    from channelgen import device_pool
+    wp = wl("precision")
+    Hp = device_pool(wp.M, wp.S, wp.K, wp.r, wp.vr, wp.batch, 7)
+    Wp = torch.empty_like(Hp)
+    X64 = torch.empty((wp.batch, wp.K, wp.K), dtype=torch.complex128, device="cuda")
+    run = lambda: bd.rzf_precoder(sess, Hp, 12.8, tol=1e-6, max_iter=64, precision=bd.GRAM_FP32 | bd.REFINE_FP64,
+                                  W=Wp, X64_out=X64, stats=True, stream=stream)
+    run()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        _, pst, _ = run()
+    ms_p = (time.perf_counter() - t0) * 1e3 / 3
+    errs = []
+    for b in (0, wp.batch - 1):
+        Hb = Hp[b].cpu().numpy().T.astype(np.complex128)
+        Xs, Ws, _ = oracle.direct_rzf(Hb, 12.8)
+        errs.append((float(np.linalg.norm(X64[b].cpu().numpy().T - Xs) / np.linalg.norm(Xs)),
+                     float(np.linalg.norm(Wp[b].cpu().numpy().T - Ws) / np.linalg.norm(Ws))))
+    out["precision_refined"] = {"ms": round(ms_p, 3), "precoders_per_s": round(wp.batch / (ms_p / 1e3), 1),
+                                "max_iters": pst["max_iters"], "refine_steps": pst["refine_steps"],
+                                "max_refine_residual": pst["max_refine_residual"],
+                                "sampled_err_X64_vs_fp64": max(e[0] for e in errs),
+                                "sampled_err_W_vs_fp64": max(e[1] for e in errs),
+                                "config": "256 x (M=4096 = 16 x 256, K=128), r=0.7, regions of 6-12, xi=12.8, "
+                                          "FP32 PCG to 1e-6 + FP64 refinement to 1e-10 (host-synchronised)"}
+    del Hp, Wp, X64
 
     # Jacobi-PCG vs plain CG on the gain-normalised channels at 20 dB, where
     # the users' gains (the diagonal of A) spread and the systems are not ~xi I
@@ -373,6 +427,7 @@ def main():
     cpu, err_T, err_64, best = (None, None, None, None)
     if not a.no_cpu:
         cpu, err_T, err_64 = cpu_baseline(H_host, xi, T, W.cpu().numpy(), a.cpu_seconds)
+        cpu["other_workloads"] = oracle_other_workloads()
         best = cpu_best(H_host, xi)
 
     rows = next_rows(bd, torch, sess, H, xi, stream) if not a.no_rows else None
