@@ -55,12 +55,16 @@ def parse():
 PEAK_BF16_MFMA_TFLOPS = 2500.0    # MI355X dense BF16 matrix peak
 
 
-def algorithmic(M, K, n, T, batch, gram, epilogue):
+def algorithmic(M, K, n, T, batch, gram, epilogue, T_exec=None):
     """Per launch: algorithmic flops and HBM bytes of each kernel, and the work
     its instructions actually execute on the matrix cores.
 
-    Split-BF16 kernels execute `products` bf16 MFMA products per FP32 product
-    (3 for hi+lo, 6 for the exact three-part split)."""
+    T is the mean number of solver iterations per column (useful work);
+    T_exec (default T) the mean over 32-column blocks of the block's largest
+    count, which is what the solver executes. Split-BF16 kernels execute
+    `products` bf16 MFMA products per FP32 product (3 for hi+lo, 6 for the
+    exact three-part split)."""
+    T_exec = T if T_exec is None else T_exec
     kp = -(-K // 32) * 32
     gram_products = {"fp32": 1, "bf16x3": 3, "bf16x6": 6}[gram]
     ep_products = 6 if epilogue == "split" else 1
@@ -69,7 +73,7 @@ def algorithmic(M, K, n, T, batch, gram, epilogue):
                      exec_flops=batch * 8.0 * M * kp * (kp + 32) / 2 * gram_products,
                      dtype="fp32" if gram == "fp32" else "bf16"),
         "solve": dict(flops=batch * T * 8.0 * K * K * n, bytes=batch * (8.0 * K * K + 8.0 * K * n),
-                      exec_flops=batch * (T + 1) * 8.0 * kp * kp * n, dtype="fp32"),
+                      exec_flops=batch * (T_exec + 1) * 8.0 * kp * kp * n, dtype="fp32"),
         "epilogue": dict(flops=batch * 8.0 * M * K * n, bytes=batch * (8.0 * M * K + 8.0 * K * n + 8.0 * M * n),
                          exec_flops=batch * 8.0 * M * kp * n * ep_products,
                          dtype="fp32" if epilogue == "fp32" else "bf16"),
@@ -149,35 +153,141 @@ def oracle_other_workloads():
 
 
 def cpu_best(H_host, xi, n=64):
-    """A vectorised direct CPU path (complex64 batched Gram, LAPACK Cholesky
-    solve, power normalisation) on n instances, with all BLAS threads and with
-    one: a CPU throughput figure beside the oracle's."""
+    """A vectorised direct CPU path (batched Gram, LAPACK LU solve, power
+    normalisation) on n instances, in complex64 and complex128, with all BLAS
+    threads and with one: a CPU throughput figure beside the oracle's."""
     from threadpoolctl import threadpool_info, threadpool_limits
-    Hm = np.ascontiguousarray(np.transpose(H_host[:n], (0, 2, 1)))            # [n, M, K]
-    K = Hm.shape[2]
-
-    def run():
-        A = np.matmul(np.conj(np.transpose(Hm, (0, 2, 1))), Hm) + xi * np.eye(K, dtype=np.complex64)
-        X = np.linalg.solve(A, np.broadcast_to(np.eye(K, dtype=np.complex64), A.shape))
-        F = np.matmul(Hm, X)
-        return F / np.sqrt(np.sum(np.abs(F) ** 2, axis=(1, 2)))[:, None, None]
-
     out = {}
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-    for label, lim in (("all_cores", None), ("one_core", 1)):
-        with threadpool_limits(limits=lim):
-            run()
-            reps, t0 = 0, time.perf_counter()
-            while reps < 3 or time.perf_counter() - t0 < 2.0:
+    for dt, prefix in ((np.complex64, ""), (np.complex128, "c128_")):
+        Hm = np.ascontiguousarray(np.transpose(H_host[:n], (0, 2, 1))).astype(dt)            # [n, M, K]
+        K = Hm.shape[2]
+
+        def run():
+            A = np.matmul(np.conj(np.transpose(Hm, (0, 2, 1))), Hm) + xi * np.eye(K, dtype=dt)
+            X = np.linalg.solve(A, np.broadcast_to(np.eye(K, dtype=dt), A.shape))
+            F = np.matmul(Hm, X)
+            return F / np.sqrt(np.sum(np.abs(F) ** 2, axis=(1, 2)))[:, None, None]
+
+        for label, lim in (("all_cores", None), ("one_core", 1)):
+            with threadpool_limits(limits=lim):
                 run()
-                reps += 1
-            out[label] = round(n * reps / (time.perf_counter() - t0), 1)
-    out.update(unit="precoders/s", threads=int(threads), kind="numpy complex64 direct (batched LU solve)",
+                reps, t0 = 0, time.perf_counter()
+                while reps < 3 or time.perf_counter() - t0 < 2.0:
+                    run()
+                    reps += 1
+                out[prefix + label] = round(n * reps / (time.perf_counter() - t0), 1)
+    out.update(unit="precoders/s", threads=int(threads),
+               kind="numpy direct (batched LU solve): complex64, and complex128 under c128_",
                sample=f"{n} instances")
     return out
 
 
-def next_rows(bd, torch, sess, H, xi, stream, reps=20):
+def progress(msg):
+    """One progress line on stderr (the JSON result is the only stdout line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def _rel(a, b):
+    nb = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))
+
+
+def sample_errors(samples, rows):
+    """CPU leg: the accuracy checks of the GPU results kept in `samples`
+    (relative Frobenius error against the oracle's FP64 direct precoder, or
+    against the oracle's Jacobi-PCG at the same iteration count), the maximum
+    per (row, field) written into `rows`."""
+    import oracle
+    worst = {}
+    for smp in samples:
+        Hb = np.asarray(smp["H"]).T.astype(np.complex128)
+        direct = oracle.direct_rzf(Hb, smp["xi"]) if any(k != "W_oracle_T" for _, k, _ in smp["checks"]) else None
+        for field, kind, val in smp["checks"]:
+            if kind == "W_fp64":
+                e = _rel(val, direct[1])
+            elif kind == "X_fp64":
+                e = _rel(val, direct[0])
+            else:
+                e = _rel(val, oracle.rzf(Hb, smp["xi"], tol=0.0, max_iter=smp["T"])["W"])
+            key = (smp["path"], field)
+            worst[key] = max(worst.get(key, 0.0), e)
+    for (path, field), e in worst.items():
+        d = rows
+        for p in path:
+            d = d[p]
+        d[field] = e
+
+
+def headline_variants(bd, torch, sess, H, H_host, stream, samples, reps=20):
+    """The headline shape at every SNR of the workload (0, 10, 20 dB; xi =
+    K/SNR), for literal and gain-normalised channels: time per batch at T = 8
+    and at relative residual 1e-5, and the iterations run. Two instances of
+    each are kept in `samples` for the CPU leg's accuracy checks (against the
+    FP64 direct precoder, and against the oracle at T = 8)."""
+    from channelgen import channel_batch, workload
+    batch, K, M = H.shape
+    out = {}
+    for gain in ("literal", "normalised"):
+        if gain == "literal":
+            Hd, Hh = H, H_host
+        else:
+            Hh = channel_batch(workload("batched", gain="normalised"))
+            Hd = torch.from_numpy(Hh).to("cuda")
+        W = torch.empty_like(Hd)
+        for snr in (0.0, 10.0, 20.0):
+            xi = K / 10 ** (snr / 10.0)
+            rec = {"xi": xi}
+            for mode, kw in (("T8", dict(tol=0.0, max_iter=8)), ("tol_1e-5", dict(tol=1e-5, max_iter=64))):
+                run = lambda: bd.rzf_precoder(sess, Hd, xi, precision=bd.GRAM_BF16X6, W=W, stream=stream, **kw)
+                run()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    run()
+                torch.cuda.synchronize()
+                ms = (time.perf_counter() - t0) * 1e3 / reps
+                _, st, _ = bd.rzf_precoder(sess, Hd, xi, precision=bd.GRAM_BF16X6, W=W, stats=True, stream=stream,
+                                           **kw)
+                torch.cuda.synchronize()
+                rec[mode] = {"ms": round(ms, 4), "precoders_per_s": round(batch / (ms / 1e3), 1),
+                             "max_iters": st["max_iters"]}
+                for b in (0, batch - 1):
+                    checks = [("sampled_err_vs_fp64", "W_fp64", W[b].cpu().numpy().T)]
+                    if mode == "T8":
+                        checks.append(("sampled_err_vs_oracle_same_T", "W_oracle_T", checks[0][2]))
+                    samples.append(dict(path=("headline_variants", f"{gain}_{snr:g}dB", mode), H=Hh[b], xi=xi,
+                                        T=8, checks=checks))
+            out[f"{gain}_{snr:g}dB"] = rec
+        del W
+    return out
+
+
+def single_call_latency(bd, torch, sess, reps=200):
+    """One instance of M=256, K=16 (4 subarrays of 64, 10 dB), Jacobi-PCG to
+    relative residual 1e-6 or 16 iterations: per-call latency of rzf_precoder
+    (graph replayed), p50 / p99 over reps, host-synchronised per call."""
+    from channelgen import channel_batch, workload
+    w = workload("single")
+    Hd = torch.from_numpy(channel_batch(w)).to("cuda")
+    xi = w.xi_values()[0]
+    W = torch.empty_like(Hd)
+    run = lambda: bd.rzf_precoder(sess, Hd, xi, tol=w.tol, max_iter=w.max_iter, precision=bd.GRAM_FP32, W=W)
+    for _ in range(5):
+        run()
+    torch.cuda.synchronize()
+    lat = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        run()
+        torch.cuda.synchronize()
+        lat.append((time.perf_counter() - t0) * 1e3)
+    lat = np.array(lat)
+    return {"p50_ms": round(float(np.percentile(lat, 50)), 4), "p99_ms": round(float(np.percentile(lat, 99)), 4),
+            "config": f"1 x (M={w.M}, K={w.K}), 10 dB, tol {w.tol:g} or {w.max_iter} iterations, FP32 Gram"}
+
+
+def next_rows(bd, torch, sess, H, xi, stream, samples, reps=20):
     """Throughput of the adjacent rows on the headline channels: per-symbol
     transmission (one symbol vector per instance), the subarray-block
     precoder, the SINR / sum-rate evaluator, and Jacobi-PCG vs plain CG
@@ -245,40 +355,47 @@ def next_rows(bd, torch, sess, H, xi, stream, reps=20):
     _, vst, _ = bd.rzf_precoder_vr(sess, Hs, ws.xi, user_span=spans, tol=1e-6, max_iter=1024, W=Ws, stats=True,
                                    stream=stream)
     vr["max_iters_to_1e-6"] = vst["max_iters"]
+    samples.append(dict(path=("vr_sparse",), H=Hs_np[0], xi=ws.xi, T=None,
+                        checks=[("sampled_err_W_vs_fp64", "W_fp64", Ws[0].cpu().numpy().T)]))
     vr["config"] = "stress: 64 x (M=8192, K=256), r=0.95, regions of 1-3 of 32 subarrays, xi=1e-3, users in region order, FP32 Gram, tol 1e-6"
     out["vr_sparse"] = vr
     del Hs, Ws
 
-    # Precision workload: 256 x (M=4096, K=128), r=0.7, 10 dB, FP32 Gram and
-    # PCG to 1e-6 plus FP64-residual refinement to 1e-10 (channels of the same
-    # law drawn on the device); error of sampled results against the FP64
-    # direct precoder (oracle, CPU)
-    import oracle
+    # Precision workload: 256 x (M=4096, K=128), r=0.7, 10 dB, FP32 or
+    # two-part split-BF16 Gram, PCG to 1e-6 plus FP64-residual refinement to
+    # 1e-10 (channels of the same law drawn on the device); two instances are
+    # kept for the CPU leg's check against the FP64 direct precoder, before and
+    # after refinement
     from channelgen import device_pool
     wp = wl("precision")
     Hp = device_pool(wp.M, wp.S, wp.K, wp.r, wp.vr, wp.batch, 7)
     Wp = torch.empty_like(Hp)
     X64 = torch.empty((wp.batch, wp.K, wp.K), dtype=torch.complex128, device="cuda")
-    run = lambda: bd.rzf_precoder(sess, Hp, 12.8, tol=1e-6, max_iter=64, precision=bd.GRAM_FP32 | bd.REFINE_FP64,
-                                  W=Wp, X64_out=X64, stats=True, stream=stream)
-    run()
-    t0 = time.perf_counter()
-    for _ in range(3):
-        _, pst, _ = run()
-    ms_p = (time.perf_counter() - t0) * 1e3 / 3
-    errs = []
-    for b in (0, wp.batch - 1):
-        Hb = Hp[b].cpu().numpy().T.astype(np.complex128)
-        Xs, Ws, _ = oracle.direct_rzf(Hb, 12.8)
-        errs.append((float(np.linalg.norm(X64[b].cpu().numpy().T - Xs) / np.linalg.norm(Xs)),
-                     float(np.linalg.norm(Wp[b].cpu().numpy().T - Ws) / np.linalg.norm(Ws))))
-    out["precision_refined"] = {"ms": round(ms_p, 3), "precoders_per_s": round(wp.batch / (ms_p / 1e3), 1),
-                                "max_iters": pst["max_iters"], "refine_steps": pst["refine_steps"],
-                                "max_refine_residual": pst["max_refine_residual"],
-                                "sampled_err_X64_vs_fp64": max(e[0] for e in errs),
-                                "sampled_err_W_vs_fp64": max(e[1] for e in errs),
-                                "config": "256 x (M=4096 = 16 x 256, K=128), r=0.7, regions of 6-12, xi=12.8, "
-                                          "FP32 PCG to 1e-6 + FP64 refinement to 1e-10 (host-synchronised)"}
+    picks = (0, wp.batch - 1)
+    Hpick = {b: Hp[b].cpu().numpy() for b in picks}
+    for label, gp in (("precision_refined", bd.GRAM_FP32), ("precision_refined_bf16x3", bd.GRAM_BF16X3)):
+        # before refinement: the FP32-PCG precoder of this Gram
+        bd.rzf_precoder(sess, Hp, 12.8, tol=1e-6, max_iter=64, precision=gp, W=Wp, stream=stream)
+        torch.cuda.synchronize()
+        pre = {b: Wp[b].cpu().numpy().T for b in picks}
+        run = lambda: bd.rzf_precoder(sess, Hp, 12.8, tol=1e-6, max_iter=64, precision=gp | bd.REFINE_FP64,
+                                      W=Wp, X64_out=X64, stats=True, stream=stream)
+        run()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            _, pst, _ = run()
+        ms_p = (time.perf_counter() - t0) * 1e3 / 3
+        for b in picks:
+            samples.append(dict(path=(label,), H=Hpick[b], xi=12.8, T=None, checks=[
+                ("sampled_err_W_vs_fp64_before_refinement", "W_fp64", pre[b]),
+                ("sampled_err_X64_vs_fp64", "X_fp64", X64[b].cpu().numpy().T),
+                ("sampled_err_W_vs_fp64", "W_fp64", Wp[b].cpu().numpy().T)]))
+        out[label] = {"ms": round(ms_p, 3), "precoders_per_s": round(wp.batch / (ms_p / 1e3), 1),
+                      "max_iters": pst["max_iters"], "refine_steps": pst["refine_steps"],
+                      "max_refine_residual": pst["max_refine_residual"],
+                      "config": "256 x (M=4096 = 16 x 256, K=128), r=0.7, regions of 6-12, xi=12.8, "
+                                + ("FP32" if gp == bd.GRAM_FP32 else "split-BF16 (two parts)")
+                                + " Gram, FP32 PCG to 1e-6 + FP64 refinement to 1e-10 (host-synchronised)"}
     del Hp, Wp, X64
 
     # Jacobi-PCG vs plain CG on the gain-normalised channels at 20 dB, where
@@ -355,6 +472,7 @@ def main():
     wall = time.perf_counter() - t0
     sess.set_profiling(False)
     phases = sess.phase_times(reset=True)
+    progress(f"{a.steps} timed steps: {wall * 1e3 / a.steps:.4f} ms per step")
     lat = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(a.steps)])
     ms_per_step = wall * 1e3 / a.steps
     value = batch / (wall / a.steps)
@@ -384,6 +502,7 @@ def main():
     step()
     torch.cuda.synchronize()
 
+    progress("graph replay and tolerance variant done")
     # plain path: one instance at a time, one launch per iteration
     plain_value, same = None, None
     if a.plain_steps > 0:
@@ -398,8 +517,22 @@ def main():
         plain_value = batch / (plain_ms / 1e3)
         same = float(torch.linalg.vector_norm(W - W_plain) / torch.linalg.vector_norm(W_plain))
 
+    # Iterations the solver runs on these channels: a column stops before T
+    # once its residual is below 2^-40 of its right-hand side (FP32 range
+    # guard), and a 32-column block runs until its last column stops.
+    A_h = bd.jacpcg_gram(sess, H, xi, precision=prec, stream=stream)
+    its = torch.zeros((batch, K), dtype=torch.int32, device="cuda")
+    bd.jacpcg_solve(sess, A_h, None, tol=0.0, max_iter=T, iters=its, stream=stream)
+    torch.cuda.synchronize()
+    itn = its.cpu().numpy()
+    nb = -(-K // 32)
+    blocks = np.zeros((batch, nb * 32), dtype=itn.dtype)
+    blocks[:, :K] = itn
+    t_alg, t_exec = float(itn.mean()), float(blocks.reshape(batch, nb, 32).max(axis=2).mean())
+    del A_h, its
+
     # roofline of the dominant kernel (and the binding roof of every kernel)
-    alg = algorithmic(M, K, K, T, batch, a.gram, a.epilogue)
+    alg = algorithmic(M, K, K, t_alg, batch, a.gram, a.epilogue, T_exec=t_exec)
     per_launch = {k: (phases[k][0] / phases[k][1]) if phases[k][1] else 0.0 for k in ("gram", "solve", "epilogue")}
     kernels = {}
     for k in ("gram", "solve", "epilogue"):
@@ -412,6 +545,8 @@ def main():
                       "alg_tflops": round(alg[k]["flops"] / d / 1e12, 2),
                       "alg_GBs": round(alg[k]["bytes"] / d / 1e9, 1),
                       "mfma_dtype": alg[k]["dtype"]}
+        if k == "solve":
+            kernels[k].update(iters_mean=round(t_alg, 3), iters_per_block=round(t_exec, 3))
     dom = max(per_launch, key=per_launch.get)
     dur_s = per_launch[dom] / 1e3
     bound, _ = binding_roof(alg[dom])
@@ -424,16 +559,29 @@ def main():
                 "frac": round(achieved / peak, 4), "traffic": traffic_for(dom), "kernel": dom,
                 "avg_launch_us": round(per_launch[dom] * 1e3, 2)}
 
+    W_host = W.cpu().numpy()
+    rows, samples = None, []
+    if not a.no_rows:
+        progress("adjacent rows")
+        rows = next_rows(bd, torch, sess, H, xi, stream, samples)
+        progress("headline variants (SNR, gain)")
+        rows["headline_variants"] = headline_variants(bd, torch, sess, H, H_host, stream, samples)
+        rows["single_call"] = single_call_latency(bd, torch, sess)
+
+    # CPU leg: the oracle timed on a bounded sample, a vectorised CPU path, and
+    # the accuracy checks of sampled GPU results against the oracle
     cpu, err_T, err_64, best = (None, None, None, None)
     if not a.no_cpu:
-        cpu, err_T, err_64 = cpu_baseline(H_host, xi, T, W.cpu().numpy(), a.cpu_seconds)
+        progress("CPU leg: oracle timing, CPU direct path, accuracy checks")
+        cpu, err_T, err_64 = cpu_baseline(H_host, xi, T, W_host, a.cpu_seconds)
         cpu["other_workloads"] = oracle_other_workloads()
         best = cpu_best(H_host, xi)
-
-    rows = next_rows(bd, torch, sess, H, xi, stream) if not a.no_rows else None
+        if rows is not None:
+            sample_errors(samples, rows)
 
     serving = None
     if a.serve_seconds > 0:
+        progress("serving stream")
         from paper_2305_13925_amd.serve import run_serving
         sv = bd.Session(0, hbm_budget_bytes=64 << 30)
         serving = run_serving(sv, rate_hz=2000.0, warmup_s=0.5, measure_s=a.serve_seconds, seed=0)
@@ -454,7 +602,8 @@ def main():
         "dtype": "c64",
         "data": "synthetic",
         "config": {"workload": f"batched: {batch} x (M={M}, K={K}), 8 subarrays of 128, r=0.5, VR 3-6, "
-                               f"{a.gain} gain, SNR {a.snr_db:g} dB (xi={xi:g}), B=I_K, T={T} fixed",
+                               f"{a.gain} gain, SNR {a.snr_db:g} dB (xi={xi:g}), B=I_K, T={T} (a column stops "
+                               f"earlier once its residual is below 2^-40 of its right-hand side)",
                    "batch": batch, "M": M, "K": K, "iterations": T, "gram": a.gram, "epilogue": a.epilogue},
         "plain_value": round(plain_value, 1) if plain_value else None,
         "speedup_vs_plain": round(value / plain_value, 2) if plain_value else None,

@@ -10,6 +10,13 @@
         directory), each scaled by what the same counter reads for a plain copy
         kernel of N bytes read and N bytes written. Writes <out>.json (read by
         bench.py; tied to the sha256 of the kernel sources) and <out>.md.
+
+    python -m paper_2305_13925_amd.profile_summary busy <pmc dir> --cmd C --out profiles/mfma_busy
+        matrix-core utilisation and clock of the Gram, PCG and precoder
+        kernels from a pass with GRBM_GUI_ACTIVE and SQ_VALU_MFMA_BUSY_CYCLES:
+        clock = GRBM_GUI_ACTIVE / XCDs / dispatch duration, MFMA busy =
+        SQ_VALU_MFMA_BUSY_CYCLES / (SIMDs x GRBM_GUI_ACTIVE / XCDs), with the
+        XCD and SIMD counts read from the pass's agent info.
 """
 
 from __future__ import annotations
@@ -130,6 +137,45 @@ def traffic(a):
     print("\n".join(lines))
 
 
+def busy(a):
+    rows = counter_rows(a.dir)
+    files = glob.glob(os.path.join(a.dir, "**", "*agent_info.csv"), recursive=True)
+    gpu = [r for r in csv.DictReader(open(files[0])) if int(r.get("Simd_Count") or 0) > 0][0]
+    n_xcd, n_simd = int(gpu["Num_Xcc"]), int(gpu["Simd_Count"])
+    disp = collections.defaultdict(dict)
+    for r in rows:
+        did = r.get("Dispatch_Id") or r.get("Correlation_Id")
+        d = disp[did]
+        d["key"] = (r["Kernel_Name"], grid_of(r))
+        d["us"] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+        d[r["Counter_Name"]] = d.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    per = collections.defaultdict(list)
+    for d in disp.values():
+        per[d["key"]].append(d)
+    lines = ["# Matrix-core utilisation and clock per launch (rocprofv3 counters)\n",
+             "Command (run from the repository root on one MI355X):\n", "```", a.cmd, "```\n",
+             f"Device: {n_xcd} XCDs, {n_simd} SIMDs. Clock = GRBM_GUI_ACTIVE / {n_xcd} / dispatch duration. "
+             f"MFMA busy = SQ_VALU_MFMA_BUSY_CYCLES / ({n_simd} x GRBM_GUI_ACTIVE / {n_xcd}). The durations are "
+             "those of the counter pass, which serialises dispatches.\n",
+             "| phase | kernel | grid | dispatches | avg us | clock GHz | MFMA busy |", "|---|---|---|---|---|---|---|"]
+    rec = {}
+    for phase, prefix in PHASE_PREFIX.items():
+        k, v = largest(per, prefix)
+        if not v:
+            continue
+        us = sum(d["us"] for d in v) / len(v)
+        cyc = sum(d.get("GRBM_GUI_ACTIVE", 0.0) for d in v) / len(v) / n_xcd
+        mfma = sum(d.get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0) for d in v) / len(v)
+        ghz = cyc / (us * 1e3) if us > 0 else 0.0
+        frac = mfma / (n_simd * cyc) if cyc > 0 else 0.0
+        rec[phase] = {"kernel": short_name(k[0]), "us": us, "clock_ghz": ghz, "mfma_busy": frac}
+        lines.append(f"| {phase} | `{short_name(k[0])[:60]}` | {k[1]} | {len(v)} | {us:.1f} | {ghz:.2f} | "
+                     f"{frac:.3f} |")
+    json.dump(dict(rec, command=a.cmd), open(a.out + ".json", "w"), indent=1)
+    open(a.out + ".md", "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd_name", required=True)
@@ -144,7 +190,13 @@ def main(argv=None):
     f.add_argument("--copy-bytes", type=float, required=True)
     f.add_argument("--cmd", required=True)
     f.add_argument("--out", required=True)
+    b = sub.add_parser("busy")
+    b.add_argument("dir")
+    b.add_argument("--cmd", required=True)
+    b.add_argument("--out", required=True)
     a = ap.parse_args(argv)
+    if a.cmd_name == "busy":
+        return busy(a)
     if a.cmd_name == "trace":
         text = trace_table(a.csv, a.title, a.cmd)
         if a.out:
