@@ -304,7 +304,12 @@ int rzf_sinr(jacpcg_session* s, void* stream, int batch, int M, int K,
  * H: device, n_sub instances of column-major M x K complex64 (ld M, stride
  * M*K). W: device output of the same layout. Both buffers are owned by the
  * caller and must stay alive until jacpcg_poll / jacpcg_wait returns a final
- * result for the request. */
+ * result for the request.
+ * stream: the stream on which the caller writes H (NULL: the default stream).
+ * jacpcg_submit records an event on it, and the request's device work waits
+ * for that event: H may still be in production when the request is
+ * submitted, and work queued on `stream` after the submission is not waited
+ * for. W is complete when the result is final. */
 typedef struct {
   int M, K, n_sub;
   const jacpcg_c64* H;
@@ -312,6 +317,7 @@ typedef struct {
   double xi, power, tol;
   int max_iter, precision, flags;
   uint64_t user_tag;
+  hipStream_t stream;
 } jacpcg_request;
 
 /* Result of a request. status: the request's worst per-instance status (OK,
@@ -333,7 +339,8 @@ typedef struct {
  * concurrently. A request's result does not depend on what it is batched with.
  * Errors: E_INVALID_ARG (sizes, NULL buffers, xi < 0, power <= 0, tol < 0,
  * max_iter < 0, unknown flags), E_UNSUPPORTED (refinement requested),
- * E_BUDGET (the request alone needs more than the session budget). */
+ * E_BUDGET (the request alone needs more than the session budget), E_HIP (the
+ * event on the request's stream could not be recorded). */
 int jacpcg_submit(jacpcg_session* s, const jacpcg_request* r, uint64_t* ticket);
 
 /* Non-blocking: NOT_READY while the request is queued or running; OK once final

@@ -69,7 +69,7 @@ class JacpcgStats(C.Structure):
 class JacpcgRequest(C.Structure):
     _fields_ = [("M", C.c_int), ("K", C.c_int), ("n_sub", C.c_int), ("H", C.c_void_p), ("W", C.c_void_p),
                 ("xi", C.c_double), ("power", C.c_double), ("tol", C.c_double), ("max_iter", C.c_int),
-                ("precision", C.c_int), ("flags", C.c_int), ("user_tag", C.c_uint64)]
+                ("precision", C.c_int), ("flags", C.c_int), ("user_tag", C.c_uint64), ("stream", C.c_void_p)]
 
 
 class JacpcgResult(C.Structure):
@@ -429,15 +429,17 @@ def rzf_sinr(session, H, W, sigma2, sinr=None, se=None, stream=None):
 
 
 def jacpcg_submit(session, H, W, xi, power=1.0, tol=0.0, max_iter=16, precision=GRAM_FP32, flags=PRECOND_JACOBI,
-                  user_tag=0):
+                  user_tag=0, stream=None):
     """Queue a request: H, W complex64 [n_sub, K, M] device tensors (kept alive
-    by the caller until the result is collected). Returns the ticket."""
+    by the caller until the result is collected). The request waits for the
+    work queued so far on `stream` (default: the current stream), where H is
+    produced. Returns the ticket."""
     torch = _torch()
     _require(H, "H", torch.complex64)
     n_sub, K, M = H.shape
     _require(W, "W", torch.complex64, (n_sub, K, M))
     r = JacpcgRequest(M, K, n_sub, H.data_ptr(), W.data_ptr(), float(xi), float(power), float(tol), int(max_iter),
-                      int(precision), int(flags), int(user_tag))
+                      int(precision), int(flags), int(user_tag), _stream(stream))
     t = C.c_uint64()
     _check(lib().jacpcg_submit(session.handle, C.byref(r), C.byref(t)))
     return t.value

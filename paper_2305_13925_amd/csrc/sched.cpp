@@ -63,6 +63,10 @@ void Scheduler::stop() {
   if (sched_thread_.joinable()) sched_thread_.join();
   if (comp_thread_.joinable()) comp_thread_.join();
   (void)hipSetDevice(s_->device);
+  for (auto& kv : reqs_)
+    if (kv.second.ready) give_event(kv.second.ready);
+  for (hipEvent_t e : ev_pool_) (void)hipEventDestroy(e);
+  ev_pool_.clear();
   for (auto& sl : slots_) {
     if (sl.stream) (void)hipStreamSynchronize(sl.stream);
     if (sl.done) (void)hipEventDestroy(sl.done);
@@ -72,6 +76,25 @@ void Scheduler::stop() {
     sl = Slot{};
   }
   running_ = false;
+}
+
+hipEvent_t Scheduler::take_event() {
+  if (!ev_pool_.empty()) {
+    hipEvent_t e = ev_pool_.back();
+    ev_pool_.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  (void)hipSetDevice(s_->device);
+  if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return e;
+}
+
+void Scheduler::give_event(hipEvent_t e) {
+  if (e) ev_pool_.push_back(e);
 }
 
 int Scheduler::submit(const jacpcg_request& r, uint64_t* ticket) {
@@ -106,6 +129,17 @@ int Scheduler::submit(const jacpcg_request& r, uint64_t* ticket) {
   k = mix(k, bits(r.xi));
   k = mix(k, bits(r.power));
   q.key = k;
+  // The request's device work will wait for what is queued on its stream now
+  // (the production of H).
+  q.ready = take_event();
+  if (!q.ready) return set_error(JACPCG_E_HIP, "creating the request's ready event failed");
+  (void)hipSetDevice(s_->device);
+  const hipError_t er = hipEventRecord(q.ready, r.stream);
+  if (er != hipSuccess) {
+    (void)hipGetLastError();
+    give_event(q.ready);
+    return set_error(JACPCG_E_HIP, hipGetErrorString(er));
+  }
   q.t_submit = now_us();
   const uint64_t t = next_ticket_++;
   reqs_.emplace(t, q);
@@ -170,6 +204,8 @@ int Scheduler::cancel(uint64_t ticket) {
   Req& q = it->second;
   if (q.state == kQueued) {
     queue_.erase(std::find(queue_.begin(), queue_.end(), ticket));
+    give_event(q.ready);
+    q.ready = nullptr;
     q.state = kDone;
     q.status = JACPCG_E_CANCELLED;
     q.t_done = now_us();
@@ -228,10 +264,19 @@ void Scheduler::scheduler_loop() {
       free_slot->busy = true;  // reserved; the completion thread ignores it until armed
       free_slot->bytes = bytes;
       std::vector<jacpcg_request> rq;  // copies: the map may rehash while unlocked
-      for (uint64_t t : members) rq.push_back(reqs_.at(t).r);
+      std::vector<hipEvent_t> ready;
+      for (uint64_t t : members) {
+        Req& q = reqs_.at(t);
+        rq.push_back(q.r);
+        ready.push_back(q.ready);
+        q.ready = nullptr;
+      }
       lk.unlock();
-      const int rc = launch(*free_slot, members, rq);
+      const int rc = launch(*free_slot, members, rq, ready);
       lk.lock();
+      // The slot's stream waits on the events' state at launch; later
+      // submissions may record them again.
+      for (hipEvent_t e : ready) give_event(e);
       if (rc != JACPCG_OK) {
         for (uint64_t t : members) {
           Req& q = reqs_.at(t);
@@ -252,7 +297,8 @@ void Scheduler::scheduler_loop() {
   }
 }
 
-int Scheduler::launch(Slot& sl, const std::vector<uint64_t>& members, const std::vector<jacpcg_request>& rq) {
+int Scheduler::launch(Slot& sl, const std::vector<uint64_t>& members, const std::vector<jacpcg_request>& rq,
+                      const std::vector<hipEvent_t>& ready) {
   (void)hipSetDevice(s_->device);
   const jacpcg_request& r0 = rq[0];
   const int M = r0.M, K = r0.K;
@@ -315,9 +361,13 @@ int Scheduler::launch(Slot& sl, const std::vector<uint64_t>& members, const std:
   const int ncb = (K + 31) / 32;
   const size_t KK = (size_t)K * K;
   hipStream_t st = sl.stream;
+  // Every member's H is complete (its producer stream's work at submission).
+  hipError_t e = hipSuccess;
+  for (hipEvent_t ev : ready)
+    if (e == hipSuccess && ev) e = hipStreamWaitEvent(st, ev, 0);
   // The two pointer arrays are adjacent on the host but 256-byte aligned apart
   // on the device: one copy each.
-  hipError_t e = hipMemcpyAsync((void*)d_hp, hp, (size_t)G * sizeof(void*), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync((void*)d_hp, hp, (size_t)G * sizeof(void*), hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipMemcpyAsync((void*)d_wp, wp, (size_t)G * sizeof(void*), hipMemcpyHostToDevice, st);
 
   GramLaunch g{};

@@ -49,6 +49,7 @@ class Scheduler {
     int max_iters = 0;
     bool cancelled = false;
     double t_submit = 0, t_admit = 0, t_done = 0;
+    hipEvent_t ready = nullptr;  // recorded on the request's stream at submission
   };
   struct Slot {
     hipStream_t stream = nullptr;
@@ -71,7 +72,11 @@ class Scheduler {
   void start();
   void scheduler_loop();
   void completion_loop();
-  int launch(Slot& slot, const std::vector<uint64_t>& members, const std::vector<jacpcg_request>& rq);
+  int launch(Slot& slot, const std::vector<uint64_t>& members, const std::vector<jacpcg_request>& rq,
+             const std::vector<hipEvent_t>& ready);
+  hipEvent_t take_event();             // from the pool, or a new one (lock held)
+  void give_event(hipEvent_t e);       // back to the pool (lock held)
+  std::vector<hipEvent_t> ev_pool_;
   void finish(Slot& slot);
   double now_us() const;
 

@@ -114,3 +114,22 @@ def test_short_poisson_stream(torch, sess):
     assert out["requests"] > 100
     assert out["statuses"].get(str(bd.OK), 0) + out["statuses"].get(str(bd.NOT_CONVERGED), 0) == out["requests"]
     assert out["p99_ms"] < 1000.0
+
+
+def test_request_waits_for_the_stream_that_produces_H(torch, sess):
+    # H is written on a side stream, with extra work queued behind its
+    # generation, and submitted without any synchronisation: the request must
+    # read the finished H (the ready event recorded on that stream at submission).
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        H = device_pool(2048, 4, 64, 0.5, (2, 4), 32, 11)
+        for _ in range(50):
+            H.mul_(1.0)
+        W = torch.empty_like(H)
+        t = bd.jacpcg_submit(sess, H, W, 6.4, tol=0.0, max_iter=8, stream=side)
+    res = bd.jacpcg_wait(sess, t, 20000)
+    assert res["status"] == bd.OK
+    torch.cuda.synchronize()
+    W_dir = bd.rzf_precoder(sess, H, 6.4, tol=0.0, max_iter=8)
+    torch.cuda.synchronize()
+    assert torch.equal(W, W_dir)
