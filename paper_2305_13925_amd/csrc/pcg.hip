@@ -142,7 +142,15 @@ __global__ __launch_bounds__(KT * 64) __attribute__((amdgpu_waves_per_eu(2))) vo
   const int j = cb * 32 + jl;
   const bool jvalid = j < p.nrhs;
 
-  __shared__ float2 Psh[KP][32];
+  // The direction block P, and before it (K <= 64) the staging tile of A.
+  // The direction block P; before it (K <= 64) the staging tile of 32 rows of
+  // A, after it the staging tile of X (32 columns of KP + 1 entries).
+  constexpr int kLdsP = KP * 32 * (int)sizeof(float2);
+  constexpr int kLdsA = AREG ? 32 * KP * (int)sizeof(float2) : 0;
+  constexpr int kLdsX = 32 * (KP + 1) * (int)sizeof(float2);
+  constexpr int kLds = kLdsA > kLdsX ? kLdsA : (kLdsX > kLdsP ? kLdsX : kLdsP);
+  __shared__ __attribute__((aligned(16))) unsigned char lds_raw[kLds];
+  float2(*Psh)[32] = reinterpret_cast<float2(*)[32]>(lds_raw);
   __shared__ float red[3][KT][32];
 
   const bool chunked = p.st.vec != nullptr;
@@ -169,23 +177,60 @@ __global__ __launch_bounds__(KT * 64) __attribute__((amdgpu_waves_per_eu(2))) vo
   const float2* arow_full = Ab + (int64_t)(ia < K ? ia : 0) * p.lda;
 
   float ar[AREG ? KH : 1], ai[AREG ? KH : 1];
+  float dinv[16];  // Jacobi preconditioner D^{-1} on the rows owned in the result layout
   if constexpr (AREG) {
+    // K <= 64: the workgroup reads A once with coalesced loads (consecutive
+    // threads take consecutive columns of a row), all loads in flight at once,
+    // and passes it through LDS 32 rows at a time (the rows of one wave; the
+    // tile is the memory of P): entry (i, k) of the pass at i * KP + (k ^ i),
+    // so that the lanes of one read below (32 rows, one column) hit distinct
+    // banks; zero outside K x K. Wave w takes its half-rows and the diagonal
+    // entries of its rows from pass w.
+    float2* At = reinterpret_cast<float2*>(lds_raw);
+    constexpr int kPer = 32 * KP / (KT * 64);  // entries per thread and pass
+    float2 av[KT][kPer];
 #pragma unroll
-    for (int s = 0; s < KH; ++s) {
-      const float2 v = (s < klim) ? arow[s] : make_float2(0.f, 0.f);
-      ar[s] = v.x;
-      ai[s] = v.y;
+    for (int q = 0; q < KT; ++q)
+#pragma unroll
+      for (int u = 0; u < kPer; ++u) {
+        const int e = threadIdx.x + u * KT * 64;
+        const int i = q * 32 + e / KP, k = e % KP;
+        av[q][u] = (i < K && k < K) ? Ab[(int64_t)i * p.lda + k] : make_float2(0.f, 0.f);
+      }
+#pragma unroll
+    for (int q = 0; q < KT; ++q) {
+      if (q > 0) __syncthreads();  // wave q - 1 has read the previous pass
+#pragma unroll
+      for (int u = 0; u < kPer; ++u) {
+        const int e = threadIdx.x + u * KT * 64;
+        const int i = e / KP, k = e % KP;
+        At[i * KP + (k ^ i)] = av[q][u];
+      }
+      __syncthreads();
+      if (w == q) {
+#pragma unroll
+        for (int s = 0; s < KH; ++s) {
+          const float2 v = At[jl * KP + ((half * KH + s) ^ jl)];
+          ar[s] = v.x;
+          ai[s] = v.y;
+        }
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int il = d32_row(r, half), i = w * 32 + il;
+          const float d = p.precond_none ? 1.f : At[il * KP + (i ^ il)].x;  // entry (i, i)
+          dinv[r] = (i < K) ? 1.f / d : 0.f;
+        }
+      }
     }
-  }
-
-  // Rows owned in the result layout, and the Jacobi preconditioner D^{-1}.
-  float dinv[16];
+    __syncthreads();  // the tile is read; its memory becomes P
+  } else {
 #pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const int i = w * 32 + d32_row(r, half);
-    float d = 0.f;
-    if (i < K) d = p.precond_none ? 1.f : Ab[(int64_t)i * p.lda + i].x;
-    dinv[r] = (i < K) ? 1.f / d : 0.f;
+    for (int r = 0; r < 16; ++r) {
+      const int i = w * 32 + d32_row(r, half);
+      float d = 0.f;
+      if (i < K) d = p.precond_none ? 1.f : Ab[(int64_t)i * p.lda + i].x;
+      dinv[r] = (i < K) ? 1.f / d : 0.f;
+    }
   }
 
   float xr[16], xim[16], rr[16], ri[16], pr[16], pim[16];
@@ -349,12 +394,20 @@ __global__ __launch_bounds__(KT * 64) __attribute__((amdgpu_waves_per_eu(2))) vo
   }
 
   // ---- final outputs --------------------------------------------------------
+  // X through LDS: column jl of the block at jl * (KP + 1) (distinct banks for
+  // the 32 lanes of one register), then stored with consecutive threads on
+  // consecutive rows of a column.
   float2* Xb = p.X + (int64_t)b * p.stride_x;
-  if (jvalid) {
+  {
+    float2* Xt = reinterpret_cast<float2*>(lds_raw);
+    __syncthreads();  // every wave is done with P
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int i = w * 32 + d32_row(r, half);
-      if (i < K) Xb[(int64_t)j * p.ldx + i] = make_float2(xr[r], xim[r]);
+    for (int r = 0; r < 16; ++r) Xt[jl * (KP + 1) + w * 32 + d32_row(r, half)] = make_float2(xr[r], xim[r]);
+    __syncthreads();
+    const int ncol = min(32, p.nrhs - cb * 32);
+    for (int e = threadIdx.x; e < ncol * K; e += KT * 64) {
+      const int jc = e / K, i = e - jc * K;
+      Xb[(int64_t)(cb * 32 + jc) * p.ldx + i] = Xt[jc * (KP + 1) + i];
     }
   }
   int col_status = kStatusOk;
