@@ -28,6 +28,9 @@
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream). Work
  *     is enqueued asynchronously on it; outputs are valid after the stream is
  *     synchronised, unless the entry point says it synchronises.
+ *   - The calls of one session share its workspace. A call on another stream
+ *     than the session's previous call first makes its stream wait for that
+ *     call's work, so a caller may alternate streams without synchronising.
  *   - Every call returns a status code. Argument errors are detected on the
  *     host before any device work and leave outputs untouched; the detail is
  *     available from jacpcg_last_error() on the calling thread.

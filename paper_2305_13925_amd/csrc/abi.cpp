@@ -264,13 +264,15 @@ int jacpcg_solve(jacpcg_session* s, void* stream, int batch, int K, int nrhs, co
   p.iters = iters;
   p.relres = relres;
   p.wg_status = status ? s->at<int32_t>(o_wg) : nullptr;
-  hipError_t e = s->timed(st, JACPCG_PHASE_SOLVE, [&] { return launch_pcg(p, st, nullptr); });
-  if (e != hipSuccess) return hip_fail(s, e, "pcg launch");
-  if (status) {
-    e = launch_status_reduce(p.wg_status, ncb, batch, status, st);
-    if (e != hipSuccess) return hip_fail(s, e, "status reduce launch");
-  }
-  return JACPCG_OK;
+  return s->ordered(st, [&] {
+    hipError_t e = s->timed(st, JACPCG_PHASE_SOLVE, [&] { return launch_pcg(p, st, nullptr); });
+    if (e != hipSuccess) return hip_fail(s, e, "pcg launch");
+    if (status) {
+      e = launch_status_reduce(p.wg_status, ncb, batch, status, st);
+      if (e != hipSuccess) return hip_fail(s, e, "status reduce launch");
+    }
+    return (int)JACPCG_OK;
+  });
 }
 
 int rzf_precoder(jacpcg_session* s, void* stream, int batch, int M, int K, const jacpcg_c64* H, int64_t ldh,
@@ -299,9 +301,11 @@ int rzf_precoder(jacpcg_session* s, void* stream, int batch, int M, int K, const
   }
   JP_HIP(hipSetDevice(s->device));
   hipStream_t st = (hipStream_t)stream;
-  return s->run_rzf(st, batch, M, K, (const float2*)H, ldh, stride_h, K, nullptr, 0, 0, xi, power, tol, max_iter,
-                    gram_prec, refine, (flags & JACPCG_PRECOND_NONE) != 0, (flags & JACPCG_EPILOGUE_FP32) == 0,
-                    refine_tol, (float2*)W, ldw, stride_w, (float2*)X_out, (double2*)X64_out, stats);
+  return s->ordered(st, [&] {
+    return s->run_rzf(st, batch, M, K, (const float2*)H, ldh, stride_h, K, nullptr, 0, 0, xi, power, tol, max_iter,
+                      gram_prec, refine, (flags & JACPCG_PRECOND_NONE) != 0, (flags & JACPCG_EPILOGUE_FP32) == 0,
+                      refine_tol, (float2*)W, ldw, stride_w, (float2*)X_out, (double2*)X64_out, stats);
+  });
 }
 
 int rzf_precoder_vr(jacpcg_session* s, void* stream, int batch, int M, int K, const jacpcg_c64* H, int64_t ldh,
@@ -329,10 +333,12 @@ int rzf_precoder_vr(jacpcg_session* s, void* stream, int batch, int M, int K, co
     return JACPCG_OK;
   }
   JP_HIP(hipSetDevice(s->device));
-  return s->run_rzf((hipStream_t)stream, batch, M, K, (const float2*)H, ldh, stride_h, K, nullptr, 0, 0, xi, power,
-                    tol, max_iter, gram_prec, refine, (flags & JACPCG_PRECOND_NONE) != 0,
-                    (flags & JACPCG_EPILOGUE_FP32) == 0, refine_tol, (float2*)W, ldw, stride_w, (float2*)X_out,
-                    nullptr, stats, true, user_span);
+  return s->ordered((hipStream_t)stream, [&] {
+    return s->run_rzf((hipStream_t)stream, batch, M, K, (const float2*)H, ldh, stride_h, K, nullptr, 0, 0, xi, power,
+                      tol, max_iter, gram_prec, refine, (flags & JACPCG_PRECOND_NONE) != 0,
+                      (flags & JACPCG_EPILOGUE_FP32) == 0, refine_tol, (float2*)W, ldw, stride_w, (float2*)X_out,
+                      nullptr, stats, true, user_span);
+  });
 }
 
 int rzf_transmit(jacpcg_session* s, void* stream, int batch, int M, int K, int nsym, const jacpcg_c64* H,
@@ -365,10 +371,12 @@ int rzf_transmit(jacpcg_session* s, void* stream, int batch, int M, int K, int n
     return JACPCG_OK;
   }
   JP_HIP(hipSetDevice(s->device));
-  return s->run_rzf((hipStream_t)stream, batch, M, K, (const float2*)H, ldh, stride_h, nsym, (const float2*)S, lds,
-                    stride_s, xi, power, tol, max_iter, precision & 0xff, false, (flags & JACPCG_PRECOND_NONE) != 0,
-                    (flags & JACPCG_EPILOGUE_FP32) == 0, 0.0, (float2*)x, ldx, stride_x, (float2*)w_out, nullptr,
-                    stats);
+  return s->ordered((hipStream_t)stream, [&] {
+    return s->run_rzf((hipStream_t)stream, batch, M, K, (const float2*)H, ldh, stride_h, nsym, (const float2*)S, lds,
+                      stride_s, xi, power, tol, max_iter, precision & 0xff, false, (flags & JACPCG_PRECOND_NONE) != 0,
+                      (flags & JACPCG_EPILOGUE_FP32) == 0, 0.0, (float2*)x, ldx, stride_x, (float2*)w_out, nullptr,
+                      stats);
+  });
 }
 
 int rzf_precoder_plain(jacpcg_session* s, void* stream, int batch, int M, int K, const jacpcg_c64* H, int64_t ldh,
@@ -390,9 +398,11 @@ int rzf_precoder_plain(jacpcg_session* s, void* stream, int batch, int M, int K,
     return JACPCG_OK;
   }
   JP_HIP(hipSetDevice(s->device));
-  return s->run_rzf_plain((hipStream_t)stream, batch, M, K, (const float2*)H, ldh, stride_h, xi, power, tol,
-                          max_iter, (flags & JACPCG_PRECOND_NONE) != 0, (flags & JACPCG_EPILOGUE_FP32) == 0,
-                          (float2*)W, ldw, stride_w, (float2*)X_out, stats);
+  return s->ordered((hipStream_t)stream, [&] {
+    return s->run_rzf_plain((hipStream_t)stream, batch, M, K, (const float2*)H, ldh, stride_h, xi, power, tol, max_iter,
+                            (flags & JACPCG_PRECOND_NONE) != 0, (flags & JACPCG_EPILOGUE_FP32) == 0, (float2*)W, ldw,
+                            stride_w, (float2*)X_out, stats);
+  });
 }
 
 int rzf_block_precoder(jacpcg_session* s, void* stream, int batch, int M1, int Mc, int M2, int K1, int K2,
@@ -423,9 +433,11 @@ int rzf_block_precoder(jacpcg_session* s, void* stream, int batch, int M1, int M
     return JACPCG_OK;
   }
   JP_HIP(hipSetDevice(s->device));
-  return s->run_block((hipStream_t)stream, batch, M1, Mc, M2, K1, K2, (const float2*)H, ldh, stride_h, xi, power,
-                      tol, max_iter, gram_prec, refine, (flags & JACPCG_PRECOND_NONE) != 0,
-                      (flags & JACPCG_EPILOGUE_FP32) == 0, refine_tol, (float2*)G, ldg, stride_g, stats);
+  return s->ordered((hipStream_t)stream, [&] {
+    return s->run_block((hipStream_t)stream, batch, M1, Mc, M2, K1, K2, (const float2*)H, ldh, stride_h, xi, power, tol,
+                        max_iter, gram_prec, refine, (flags & JACPCG_PRECOND_NONE) != 0,
+                        (flags & JACPCG_EPILOGUE_FP32) == 0, refine_tol, (float2*)G, ldg, stride_g, stats);
+  });
 }
 
 int rzf_sinr(jacpcg_session* s, void* stream, int batch, int M, int K, const jacpcg_c64* H, int64_t ldh,
@@ -444,8 +456,10 @@ int rzf_sinr(jacpcg_session* s, void* stream, int batch, int M, int K, const jac
   if (rc) return rc;
   if (batch == 0) return JACPCG_OK;
   JP_HIP(hipSetDevice(s->device));
-  return s->run_sinr((hipStream_t)stream, batch, M, K, (const float2*)H, ldh, stride_h, (const float2*)W, ldw,
-                     stride_w, sigma2, sinr, se);
+  return s->ordered((hipStream_t)stream, [&] {
+    return s->run_sinr((hipStream_t)stream, batch, M, K, (const float2*)H, ldh, stride_h, (const float2*)W, ldw,
+                       stride_w, sigma2, sinr, se);
+  });
 }
 
 int jacpcg_session_set_graphs(jacpcg_session* s, int enable) {
@@ -465,7 +479,9 @@ int jacpcg_autotune(jacpcg_session* s, void* stream, int batch, int M, int K, in
   rc = check_session(s);
   if (rc) return rc;
   JP_HIP(hipSetDevice(s->device));
-  return s->autotune((hipStream_t)stream, batch, M, K, precision, flags);
+  return s->ordered((hipStream_t)stream, [&] {
+    return s->autotune((hipStream_t)stream, batch, M, K, precision, flags);
+  });
 }
 
 double jacpcg_session_clock_us(jacpcg_session* s) {

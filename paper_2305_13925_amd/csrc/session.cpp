@@ -132,10 +132,18 @@ hipStream_t jacpcg_session::capture_stream() {
   return cap_stream;
 }
 
+int jacpcg_session::ordered_fail(hipError_t e) {
+  (void)hipGetLastError();
+  return set_error(JACPCG_E_HIP, hipGetErrorString(e));
+}
+
 void jacpcg_session::shutdown() {
   if (sched) sched->stop();
   sched.reset();
   (void)hipDeviceSynchronize();
+  if (order_ev) (void)hipEventDestroy(order_ev);
+  order_ev = nullptr;
+  order_valid = false;
   graph_clear();
   if (cap_stream) (void)hipStreamDestroy(cap_stream);
   cap_stream = nullptr;

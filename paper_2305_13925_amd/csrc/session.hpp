@@ -47,6 +47,35 @@ struct jacpcg_session {
 
   char* arena = nullptr;
   size_t arena_bytes = 0;
+
+  // The calls of a session share its workspace. A call on another stream than
+  // the previous call first waits for that call's work (an event recorded at
+  // the end of every call), so the streams a caller alternates between never
+  // use the workspace at the same time.
+  hipEvent_t order_ev = nullptr;
+  hipStream_t order_stream = nullptr;
+  bool order_valid = false;
+  template <class F>
+  int ordered(hipStream_t st, F&& call) {
+    if (order_valid && st != order_stream) {
+      const hipError_t e = hipStreamWaitEvent(st, order_ev, 0);
+      if (e != hipSuccess) return ordered_fail(e);
+    }
+    const int rc = call();
+    if (!order_ev && hipEventCreateWithFlags(&order_ev, hipEventDisableTiming) != hipSuccess) {
+      order_ev = nullptr;
+      (void)hipGetLastError();
+      return rc;
+    }
+    if (hipEventRecord(order_ev, st) == hipSuccess) {
+      order_stream = st;
+      order_valid = true;
+    } else {
+      (void)hipGetLastError();
+    }
+    return rc;
+  }
+  int ordered_fail(hipError_t e);
   void* pinned = nullptr;
   size_t pinned_bytes = 0;
 

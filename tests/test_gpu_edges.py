@@ -110,3 +110,23 @@ def test_padded_leading_dimensions_through_the_c_abi(torch, sess):
     # the padding between columns and instances is untouched
     pad = Wp.as_strided((batch, K, ldw - M), (sw, ldw, 1), M)
     assert torch.all(pad == complex(7.0, 7.0))
+
+
+def test_calls_on_two_streams_share_the_workspace_safely(torch, sess):
+    # A long call on stream a, then at once a short one on stream b, with the
+    # same session (workspace): b's call waits for a's, so both results equal
+    # the ones computed alone.
+    from channelgen import device_pool
+    a, b = torch.cuda.Stream(), torch.cuda.Stream()
+    H1 = device_pool(1024, 8, 64, 0.5, (3, 6), 512, 21)
+    H2 = device_pool(1024, 8, 64, 0.5, (3, 6), 64, 22)
+    torch.cuda.synchronize()
+    ref1 = bd.rzf_precoder(sess, H1, 6.4, max_iter=8)
+    ref2 = bd.rzf_precoder(sess, H2, 6.4, max_iter=8)
+    torch.cuda.synchronize()
+    W1, W2 = torch.empty_like(H1), torch.empty_like(H2)
+    for _ in range(3):
+        bd.rzf_precoder(sess, H1, 6.4, max_iter=8, W=W1, stream=a)
+        bd.rzf_precoder(sess, H2, 6.4, max_iter=8, W=W2, stream=b)
+    torch.cuda.synchronize()
+    assert torch.equal(W1, ref1) and torch.equal(W2, ref2)
