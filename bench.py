@@ -105,6 +105,28 @@ def traffic_for(kernel_phase):
     return float(v) if v is not None else None
 
 
+def stream_ceiling(torch, nbytes, reps=20):
+    """What plain device streaming reaches on this GPU for the bytes of one
+    batch of H: a copy (torch's copy kernel, read + write of nbytes each), in
+    GB/s of bytes moved."""
+    x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    out = {}
+    for name, fn, moved in (("copy_GBs", lambda: y.copy_(x), 2 * nbytes),):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        out[name] = round(moved / (e0.elapsed_time(e1) / reps * 1e-3) / 1e9, 1)
+    del x, y
+    return out
+
+
 def cpu_baseline(H_host, xi, T, W_gpu, budget_s):
     """The oracle (plain complex128 CPU implementation) on a bounded sample of
     the same workload, plus the error of the GPU precoders of that sample
@@ -558,6 +580,11 @@ def main():
     roofline = {"bound": bound, "achieved": round(achieved, 2), "peak": peak, "unit": unit,
                 "frac": round(achieved / peak, 4), "traffic": traffic_for(dom), "kernel": dom,
                 "avg_launch_us": round(per_launch[dom] * 1e3, 2)}
+    # Context for the HBM-bound kernels: plain device streaming of one batch of H
+    ceiling = stream_ceiling(torch, batch * M * K * 8)
+    roofline["stream_ceiling"] = ceiling
+    if "epilogue" in kernels:
+        kernels["epilogue"]["frac_of_copy"] = round(kernels["epilogue"]["alg_GBs"] / ceiling["copy_GBs"], 4)
 
     W_host = W.cpu().numpy()
     rows, samples = None, []
