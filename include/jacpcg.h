@@ -320,7 +320,7 @@ typedef struct {
   double xi, power, tol;
   int max_iter, precision, flags;
   uint64_t user_tag;
-  hipStream_t stream;
+  void* stream; /* hipStream_t */
 } jacpcg_request;
 
 /* Result of a request. status: the request's worst per-instance status (OK,

@@ -134,7 +134,7 @@ int Scheduler::submit(const jacpcg_request& r, uint64_t* ticket) {
   q.ready = take_event();
   if (!q.ready) return set_error(JACPCG_E_HIP, "creating the request's ready event failed");
   (void)hipSetDevice(s_->device);
-  const hipError_t er = hipEventRecord(q.ready, r.stream);
+  const hipError_t er = hipEventRecord(q.ready, (hipStream_t)r.stream);
   if (er != hipSuccess) {
     (void)hipGetLastError();
     give_event(q.ready);

@@ -2,6 +2,7 @@
 the host, before any device work (runs without a GPU)."""
 
 import ctypes as C
+import os
 import subprocess
 
 import pytest
@@ -182,3 +183,33 @@ def test_binding_fails_loudly_without_device():
     with pytest.raises(bd.JacpcgError) as ei:
         bd.Session(0)
     assert ei.value.code == bd.E_NO_DEVICE
+
+
+def test_header_compiles_as_plain_c_and_structs_match_the_binding(tmp_path):
+    # The public header needs no HIP header, and the ctypes mirrors of its
+    # structs have the C layout (size and every field offset), as compiled by gcc.
+    import ctypes as C
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("gcc not available")
+    structs = {"jacpcg_request": bd.JacpcgRequest, "jacpcg_result": bd.JacpcgResult, "jacpcg_stats": bd.JacpcgStats}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "jacpcg.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    subprocess.run([gcc, "-std=c99", "-Wall", "-Werror", "-I", os.path.join(root, "include"), str(src), "-o", str(exe)],
+                   check=True, capture_output=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l}
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == C.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
