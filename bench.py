@@ -44,7 +44,7 @@ def parse():
     ap.add_argument("--epilogue", default="split", choices=["split", "fp32"])
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the CPU oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--serve-seconds", type=float, default=3.0,
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="measured seconds of the Poisson serving stream (0: skip)")
     ap.add_argument("--no-rows", action="store_true", help="skip the adjacent rows (transmit, block, SINR)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -611,7 +611,7 @@ def main():
         progress("serving stream")
         from paper_2305_13925_amd.serve import run_serving
         sv = bd.Session(0, hbm_budget_bytes=64 << 30)
-        serving = run_serving(sv, rate_hz=2000.0, warmup_s=0.5, measure_s=a.serve_seconds, seed=0)
+        serving = run_serving(sv, rate_hz=2000.0, warmup_s=1.0, measure_s=a.serve_seconds, seed=0)
         sv.close()
         serving = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in serving.items()}
 
