@@ -96,6 +96,8 @@ struct PrecoderLaunch {
   int mtiles;                               // split-BF16: 128-antenna blocks per workgroup (0 = default rule)
   const int2* tile_span;                    // nullable (split-BF16, K > 64): user-block antenna spans; user
                                             // blocks whose span misses a workgroup's antennas are skipped
+  const int32_t* wg_status;                 // nullable: the solver's per-workgroup statuses (ncb per instance),
+  int32_t* status;                          // reduced here into the per-instance status (no separate launch)
 };
 
 struct Gram64Launch {

@@ -20,6 +20,18 @@ namespace {
 
 // beta_pow = sqrt(P / ||H X||_F^2) from the per-workgroup partial sums of the
 // solve (fixed order); 0 when H X = 0.
+// Per-instance solver status from its ncb per-workgroup statuses, by
+// severity: BREAKDOWN over NOT_CONVERGED over OK.
+__device__ __forceinline__ int instance_status(const PrecoderLaunch& e, int b) {
+  int s = kStatusOk;
+  for (int c = 0; c < e.ncb; ++c) {
+    const int v = e.wg_status[(int64_t)b * e.ncb + c];
+    if (v == kStatusBreakdown) s = kStatusBreakdown;
+    else if (v == kStatusNotConverged && s == kStatusOk) s = kStatusNotConverged;
+  }
+  return s;
+}
+
 __device__ __forceinline__ float power_factor(const PrecoderLaunch& e, int b) {
   if (e.fpart64) {
     double fs = 0.0;
@@ -50,7 +62,10 @@ __global__ __launch_bounds__(256) void precoder_f32_kernel(PrecoderLaunch e) {
   __shared__ float2 Xs[KP][NC];
 
   const float beta = power_factor(e, b);
-  if (e.beta_out && mb == 0 && cw == 0 && threadIdx.x == 0) e.beta_out[b] = beta;
+  if (mb == 0 && cw == 0 && threadIdx.x == 0) {
+    if (e.beta_out) e.beta_out[b] = beta;
+    if (e.status) e.status[b] = instance_status(e, b);
+  }
 
   gptr<const float2> Xb = as_global(e.X + (int64_t)b * e.stride_x);
   for (int idx = threadIdx.x; idx < KP * NC; idx += 256) {
@@ -251,7 +266,10 @@ __global__ __launch_bounds__(256) void precoder_bf16_kernel(PrecoderLaunch e) {
   issue(1, hrB, hiB);
 
   const float beta = power_factor(e, b);
-  if (e.beta_out && mb == 0 && cw == 0 && threadIdx.x == 0) e.beta_out[b] = beta;
+  if (mb == 0 && cw == 0 && threadIdx.x == 0) {
+    if (e.beta_out) e.beta_out[b] = beta;
+    if (e.status) e.status[b] = instance_status(e, b);
+  }
 
   gptr<const float2> Xb = as_global(e.X + (int64_t)b * e.stride_x);
   for (int idx = threadIdx.x; idx < K8 * NC; idx += 256) {

@@ -405,7 +405,6 @@ int Scheduler::launch(Slot& sl, const std::vector<uint64_t>& members, const std:
   p.gdiag = gdiag;
   p.fpart = fpart;
   if (e == hipSuccess) e = launch_pcg(p, st, nullptr);
-  if (e == hipSuccess) e = launch_status_reduce(wgs, ncb, G, status, st);
 
   PrecoderLaunch E{};
   E.H_ptrs = d_hp;
@@ -421,6 +420,8 @@ int Scheduler::launch(Slot& sl, const std::vector<uint64_t>& members, const std:
   E.nrhs = K;
   E.fpart = fpart;
   E.ncb = ncb;
+  E.wg_status = wgs;  // the precoder reduces them into the per-instance status
+  E.status = status;
   E.power = (float)r0.power;
   E.split = (r0.flags & JACPCG_EPILOGUE_FP32) ? 0 : 3;
   E.nj = s_->tuner.precoder_nj(M, K, E.split);

@@ -271,9 +271,7 @@ int jacpcg_session::run_rzf(hipStream_t st, int batch, int M, int K, const float
     p.tile_span = tspan;
     e = run(JACPCG_PHASE_SOLVE, [&] { return launch_pcg(p, q, nullptr); });
     if (e != hipSuccess) return e;
-    e = launch_status_reduce(wgs, ncb, batch, status, q);
-    if (e != hipSuccess) return e;
-    return hipSuccess;
+    return hipSuccess;  // the per-instance status is reduced by the precoder kernel
   };
   // W = beta_pow H X (and the FP64 copy of X) on stream q.
   auto enqueue_precoder = [&](hipStream_t q, bool timed_run, const double* quad64, int nq) -> hipError_t {
@@ -295,6 +293,8 @@ int jacpcg_session::run_rzf(hipStream_t st, int batch, int M, int K, const float
     E.ncb = ncb;
     E.power = (float)power;
     E.beta_out = beta;
+    E.wg_status = wgs;
+    E.status = status;
     E.split = split_epilogue ? 3 : 0;
     E.nj = tuner.precoder_nj(M, K, E.split);
     E.fpart64 = quad64;  // refined path: ||H X64||^2 from the last FP64 residual
