@@ -54,8 +54,12 @@ __global__ __launch_bounds__(256) void precoder_f32_kernel(PrecoderLaunch e) {
   const int ncw = (e.nrhs + NC - 1) / NC;
   const int per = nmb * ncw;
   const int L = xcd_remap(blockIdx.x, gridDim.x);
-  const int b = L / per;
-  const int rem = L - b * per;
+  // Instances are taken last first: the Gram launch just before this one read
+  // the channels in increasing order, so the last ones it read are the likeliest
+  // still to sit in the Infinity Cache (256 MB, shared by all XCDs).
+  const int bq = L / per;
+  const int b = e.batch - 1 - bq;
+  const int rem = L - bq * per;
   const int mb = rem / ncw, cw = rem - mb * ncw;
   const int K = e.K;
 
@@ -205,8 +209,12 @@ __global__ __launch_bounds__(256) void precoder_bf16_kernel(PrecoderLaunch e) {
   const int ncw = (e.nrhs + NC - 1) / NC;
   const int per = nmb * ncw;
   const int L = xcd_remap(blockIdx.x, gridDim.x);
-  const int b = L / per;
-  const int rem = L - b * per;
+  // Instances are taken last first: the Gram launch just before this one read
+  // the channels in increasing order, so the last ones it read are the likeliest
+  // still to sit in the Infinity Cache (256 MB, shared by all XCDs).
+  const int bq = L / per;
+  const int b = e.batch - 1 - bq;
+  const int rem = L - bq * per;
   const int mb = rem / ncw, cw = rem - mb * ncw;
   const int blk0 = mb * mt, blk1 = min(nblk, blk0 + mt);
   const int K = e.K;
