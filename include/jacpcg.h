@@ -205,6 +205,10 @@ typedef struct {
  * stats (host, nullable): when given, the call synchronises `stream` and fills
  *   it. The refined path always synchronises (host-driven convergence test).
  * Returns the worst per-instance status when it synchronises, else OK.
+ * Non-finite values in an instance's H make its A non-finite: that instance
+ *   ends with E_BREAKDOWN within max_iter and its W and X are unspecified; the
+ *   other instances are computed exactly as without it (on the refined path
+ *   they still stop on their own residuals).
  * Errors: as jacpcg_gram and jacpcg_solve; power <= 0; refine_tol < 0. */
 int rzf_precoder(jacpcg_session* s, void* stream, int batch, int M, int K,
                  const jacpcg_c64* H, int64_t ldh, int64_t stride_h,

@@ -130,3 +130,67 @@ def test_calls_on_two_streams_share_the_workspace_safely(torch, sess):
         bd.rzf_precoder(sess, H2, 6.4, max_iter=8, W=W2, stream=b)
     torch.cuda.synchronize()
     assert torch.equal(W1, ref1) and torch.equal(W2, ref2)
+
+
+@pytest.mark.parametrize("prec", [bd.GRAM_FP32, bd.GRAM_BF16X6])
+def test_non_finite_channel_is_isolated(torch, sess, prec):
+    # A NaN in one instance's channel and an Inf in another make their Gram
+    # matrices non-finite. Their solves must end with a breakdown status within
+    # max_iter, and every other instance must come out bitwise as in the same
+    # call with clean channels (instances are independent). Ragged K and M.
+    rng = np.random.default_rng(11)
+    n, K, M, xi, T = 6, 40, 200, 4.0, 8
+    Hc = torch.from_numpy(crandn(rng, n, K, M)).cuda()
+    Hb = Hc.clone()
+    Hb[2, 5, 17] = complex(float("nan"), 0.0)
+    Hb[4, 0, 0] = complex(float("inf"), 0.0)
+    good, bad = [0, 1, 3, 5], [2, 4]
+
+    W_clean = bd.rzf_precoder(sess, Hc, xi, max_iter=T, precision=prec)
+    W_bad = bd.rzf_precoder(sess, Hb, xi, max_iter=T, precision=prec)
+    torch.cuda.synchronize()
+    assert torch.equal(W_bad[good], W_clean[good])
+    assert torch.isfinite(torch.view_as_real(W_clean)).all()
+    with pytest.raises(bd.JacpcgError) as ei:  # synchronising call: the worst status is an error code
+        bd.rzf_precoder(sess, Hb, xi, max_iter=T, precision=prec, stats=True)
+    assert ei.value.code == bd.E_BREAKDOWN
+
+    # per-instance statuses and iteration counts through the solver entry point
+    A = bd.jacpcg_gram(sess, Hb, xi, precision=prec)
+    status = torch.full((n,), 99, dtype=torch.int32, device="cuda")
+    its = torch.full((n, K), -1, dtype=torch.int32, device="cuda")
+    bd.jacpcg_solve(sess, A, None, tol=1e-6, max_iter=T, iters=its, status=status)
+    torch.cuda.synchronize()
+    st = status.cpu().tolist()
+    print("non-finite: statuses", st, "max iters", int(its.max()))
+    assert [st[b] for b in bad] == [bd.E_BREAKDOWN] * 2
+    assert all(st[b] in (bd.OK, bd.NOT_CONVERGED) for b in good)
+    assert int(its.min()) >= 0 and int(its.max()) <= T
+
+    # the session is unaffected: the clean call repeats bitwise
+    W_again = bd.rzf_precoder(sess, Hc, xi, max_iter=T, precision=prec)
+    torch.cuda.synchronize()
+    assert torch.equal(W_again, W_clean)
+
+
+def test_non_finite_channel_refined_path(torch, sess):
+    # The FP64-refined path with one NaN instance: the call reports the
+    # breakdown, and the other instances still reach the FP64 direct precoder
+    # (their refinement stops on their own residuals; a NaN residual does not
+    # count towards the stopping test).
+    rng = np.random.default_rng(12)
+    n, K, M, xi = 3, 24, 160, 2.0
+    H = crandn(rng, n, K, M)
+    Hb = torch.from_numpy(H).cuda()
+    Hb[1, 3, 3] = complex(float("nan"), float("nan"))
+    W = torch.empty_like(Hb)
+    with pytest.raises(bd.JacpcgError) as ei:
+        bd.rzf_precoder(sess, Hb, xi, tol=1e-6, max_iter=64, precision=bd.GRAM_FP32 | bd.REFINE_FP64,
+                        refine_tol=1e-10, W=W, stats=True)
+    assert ei.value.code == bd.E_BREAKDOWN
+    Wn = W.cpu().numpy()
+    for b in (0, 2):
+        _, Ws, _ = oracle.direct_rzf(H[b].T.astype(np.complex128), xi)
+        err = rel(Wn[b].T, Ws)
+        print(f"non-finite refined: instance {b} W err {err:.2e}")
+        assert err <= 1e-6  # W is complex64: only its rounding remains
