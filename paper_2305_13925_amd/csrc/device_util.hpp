@@ -43,6 +43,15 @@ __device__ __forceinline__ void st4(gptr<float4> p, float a, float b, float c, f
 __device__ __forceinline__ void st2(gptr<float2> p, float re, float im) {
   *reinterpret_cast<gptr<gfloat2>>(p) = gfloat2{re, im};
 }
+// Streaming stores for outputs nothing reads back soon (the precoder W): they
+// bypass cache allocation, so no dirty lines are left for later kernels'
+// reads to write back.
+__device__ __forceinline__ void st4_nt(gptr<float4> p, float a, float b, float c, float d) {
+  __builtin_nontemporal_store(gfloat4{a, b, c, d}, reinterpret_cast<gptr<gfloat4>>(p));
+}
+__device__ __forceinline__ void st2_nt(gptr<float2> p, float re, float im) {
+  __builtin_nontemporal_store(gfloat2{re, im}, reinterpret_cast<gptr<gfloat2>>(p));
+}
 
 __device__ __forceinline__ floatx16 mfma32(float a, float b, floatx16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);

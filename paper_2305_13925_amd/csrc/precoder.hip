@@ -129,12 +129,12 @@ __global__ __launch_bounds__(256) void precoder_f32_kernel(PrecoderLaunch e) {
       const int m = m0 + 8 * g + 4 * half;
       if (VEC && m + 4 <= e.M) {
         gptr<float4> dst = reinterpret_cast<gptr<float4>>(wc + m);
-        st4(dst, wr[t][4 * g + 0], wi[t][4 * g + 0], wr[t][4 * g + 1], wi[t][4 * g + 1]);
-        st4(dst + 1, wr[t][4 * g + 2], wi[t][4 * g + 2], wr[t][4 * g + 3], wi[t][4 * g + 3]);
+        st4_nt(dst, wr[t][4 * g + 0], wi[t][4 * g + 0], wr[t][4 * g + 1], wi[t][4 * g + 1]);
+        st4_nt(dst + 1, wr[t][4 * g + 2], wi[t][4 * g + 2], wr[t][4 * g + 3], wi[t][4 * g + 3]);
       } else {
 #pragma unroll
         for (int q = 0; q < 4; ++q)
-          if (m + q < e.M) st2(wc + m + q, wr[t][4 * g + q], wi[t][4 * g + q]);
+          if (m + q < e.M) st2_nt(wc + m + q, wr[t][4 * g + q], wi[t][4 * g + q]);
       }
     }
   }
@@ -362,7 +362,7 @@ __global__ __launch_bounds__(256) void precoder_bf16_kernel(PrecoderLaunch e) {
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
           const int j = cw * NC + t * 32 + d32_row(r, half);
-          if (FULL || j < e.nrhs) st2(Wb + (int64_t)j * e.ldw, wr[t][r], wi[t][r]);
+          if (FULL || j < e.nrhs) st2_nt(Wb + (int64_t)j * e.ldw, wr[t][r], wi[t][r]);
         }
       }
     }
