@@ -15,7 +15,10 @@ namespace jacpcg {
 
 namespace {
 
-constexpr int kSlots = 8;
+// One slot per hardware queue of the process (HIP's default is 4): a fifth
+// stream would share an in-order hardware queue with the first, so a small
+// batch could wait behind a large one's kernels instead of running beside them.
+constexpr int kSlots = 4;
 
 uint64_t mix(uint64_t h, uint64_t v) {
   h ^= v + 0x9e3779b97f4a7c15ULL + (h << 6) + (h >> 2);

@@ -74,6 +74,15 @@ def run_serving(session, rate_hz=2000.0, warmup_s=1.0, measure_s=10.0, seed=0, t
     statuses = {}
     for _, r in meas:
         statuses[r["status"]] = statuses.get(r["status"], 0) + 1
+    # Latency per number of users: the stream mixes requests whose work differs
+    # by four orders of magnitude (M up to 4096, K up to 256, up to 64
+    # subcarriers), so the tail is read per size class.
+    by_k = {}
+    for K in sorted({q["K"] for q, _ in meas}):
+        lk = np.array([(r["t_done_us"] - r["t_submit_us"]) / 1e3 for q, r in meas if q["K"] == K])
+        by_k[str(K)] = {"requests": int(lk.size), "p50_ms": round(float(np.percentile(lk, 50)), 4),
+                        "p99_ms": round(float(np.percentile(lk, 99)), 4)}
+    exec_ms = np.array([(r["t_done_us"] - r["t_admit_us"]) / 1e3 for _, r in meas])
     return {
         "requests": len(meas),
         "offered_req_per_s": rate_hz,
@@ -82,6 +91,8 @@ def run_serving(session, rate_hz=2000.0, warmup_s=1.0, measure_s=10.0, seed=0, t
         "p99_ms": float(np.percentile(lat_ms, 99)),
         "max_ms": float(lat_ms.max()),
         "p99_queue_ms": float(np.percentile(queue_ms, 99)),
+        "p99_exec_ms": float(np.percentile(exec_ms, 99)),
+        "by_K": by_k,
         "statuses": {str(k): v for k, v in statuses.items()},
         "wall_s": wall,
         "max_iters": int(max(r["max_iters"] for _, r in meas)),
