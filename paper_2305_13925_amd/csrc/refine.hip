@@ -31,88 +31,138 @@ __device__ __forceinline__ void upper_tile16(int t, int nt, int& ti, int& tj) {
   tj = i + t;
 }
 
-// One workgroup per (instance, 16x16 tile of the upper triangle); 4 waves split
-// the antennas, partial tiles summed in LDS in wave order.
+// One workgroup per (instance, 64 x 64 block of the upper block triangle of A).
+// Wave w owns block rows 16w .. 16w+15 against all 64 block columns (four
+// 16 x 16 tiles, so no reduction across waves); in a diagonal block it skips
+// the tiles that lie wholly below the diagonal. The channel rows of the block
+// pass through LDS 16 antennas at a time, read from global memory with
+// coalesced 16-byte loads one stage ahead (into registers) of the products.
+constexpr int kG64Rows = 64;  // block edge
+constexpr int kG64Ant = 16;   // antennas per stage
+constexpr int kG64Pad = kG64Ant + 1;  // LDS row pitch in complex entries (bank spread)
+
 __global__ __launch_bounds__(256) void gram64_kernel(Gram64Launch g) {
-  const int nt = (g.K + 15) >> 4;
-  const int ntiles = nt * (nt + 1) / 2;
+  const int nb = (g.K + kG64Rows - 1) / kG64Rows;
+  const int nblk = nb * (nb + 1) / 2;
   const int L = xcd_remap(blockIdx.x, gridDim.x);
-  const int b = L / ntiles;
-  int ti, tj;
-  upper_tile16(L - b * ntiles, nt, ti, tj);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int b = L / nblk;
+  int bi, bj;
+  upper_tile16(L - b * nblk, nb, bi, bj);
+  const bool same = bi == bj;
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int q = lane >> 4, li = lane & 15;
   const int slot_m = q >> 1, comp = q & 1;
   const float2* Hb = g.H + (int64_t)b * g.stride_h;
-  const int ui = ti * 16 + li, uj = tj * 16 + li;
-  const bool vi = ui < g.K, vj = uj < g.K;
-  const float2* hi = Hb + (int64_t)(vi ? ui : 0) * g.ldh;
-  const float2* hj = Hb + (int64_t)(vj ? uj : 0) * g.ldh;
-  const int chunk = ((g.M + 4 * 8 - 1) / (4 * 8)) * 8;
-  const int m0 = wave * chunk;
-  const int m1 = min(g.M, m0 + chunk);
+  const bool vec = ((uintptr_t)g.H % 16 == 0) && (g.ldh % 2 == 0) && (g.stride_h % 2 == 0);
 
-  doublex4 accR = zero4d(), accI = zero4d();
-  for (int m = m0; m < m1; m += 8) {
-    float2 a[4], c[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int mm = m + 2 * u + slot_m;
-      a[u] = (vi && mm < m1) ? hi[mm] : make_float2(0.f, 0.f);
-      c[u] = (vj && mm < m1) ? hj[mm] : make_float2(0.f, 0.f);
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const double av = comp ? (double)a[u].y : (double)a[u].x;
-      const double br = comp ? (double)c[u].y : (double)c[u].x;
-      const double bi = comp ? -(double)c[u].x : (double)c[u].y;
-      accR = mfma64(av, br, accR);
-      accI = mfma64(av, bi, accI);
-    }
-  }
+  // [operand: block rows i, block columns j][row][antenna]; a diagonal block
+  // stages one operand and reads it for both.
+  __shared__ float2 Hs[2][kG64Rows][kG64Pad];
 
-  __shared__ double red[4][2][4][64];
+  // Stage loads: each thread moves 2 x 16 bytes per operand (row = e / 8,
+  // antennas 2 (e % 8) and 2 (e % 8) + 1 of the stage).
+  float4 st[2][2];
+  auto load_stage = [&](int m) {
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    red[wave][0][r][lane] = accR[r];
-    red[wave][1][r][lane] = accI[r];
-  }
-  __syncthreads();
-  // element (i, j) of the tile: lane j + 16*(i%4), register i/4
-  auto tile = [&](int i, int j, double& re, double& im) {
-    const int l = j + 16 * (i & 3), r = i >> 2;
-    re = 0.0;
-    im = 0.0;
-    for (int w = 0; w < 4; ++w) {
-      re += red[w][0][r][l];
-      im += red[w][1][r][l];
+    for (int op = 0; op < 2; ++op) {
+      if (op == 1 && same) break;  // block-uniform
+      const int blk = op == 0 ? bi : bj;
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int e = threadIdx.x + 256 * u;
+        const int row = e >> 3, a2 = 2 * (e & 7);
+        const int k = blk * kG64Rows + row, mm = m + a2;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (k < g.K) {
+          const float2* src = Hb + (int64_t)k * g.ldh + mm;
+          if (vec && mm + 2 <= g.M) {
+            v = *reinterpret_cast<const float4*>(src);
+          } else {
+            if (mm < g.M) {
+              v.x = src[0].x;
+              v.y = src[0].y;
+            }
+            if (mm + 1 < g.M) {
+              v.z = src[1].x;
+              v.w = src[1].y;
+            }
+          }
+        }
+        st[op][u] = v;
+      }
     }
   };
-  const bool same = ti == tj;
-  double2* Ab = g.A64 + (int64_t)b * g.K * g.K;
-  const int e = threadIdx.x;  // 256 threads, one tile element each
-  const int i = e >> 4, j = e & 15;
-  const int gi = ti * 16 + i, gj = tj * 16 + j;
-  if (gi < g.K && gj < g.K) {
-    double re, im;
-    if (!same || i < j) {
-      tile(i, j, re, im);
-    } else if (i > j) {
-      tile(j, i, re, im);
-      im = -im;
-    } else {
-      tile(i, i, re, im);
-      re += g.xi;
-      im = 0.0;
+  auto store_stage = [&]() {
+#pragma unroll
+    for (int op = 0; op < 2; ++op) {
+      if (op == 1 && same) break;
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int e = threadIdx.x + 256 * u;
+        const int row = e >> 3, a2 = 2 * (e & 7);
+        Hs[op][row][a2] = make_float2(st[op][u].x, st[op][u].y);
+        Hs[op][row][a2 + 1] = make_float2(st[op][u].z, st[op][u].w);
+      }
     }
-    Ab[(int64_t)gi * g.K + gj] = make_double2(re, im);
+  };
+
+  doublex4 accR[4], accI[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    accR[c] = zero4d();
+    accI[c] = zero4d();
   }
-  if (!same) {
-    const int mi = tj * 16 + i, mj = ti * 16 + j;
-    if (mi < g.K && mj < g.K) {
-      double re, im;
-      tile(j, i, re, im);
-      Ab[(int64_t)mi * g.K + mj] = make_double2(re, -im);
+  const int opj = same ? 0 : 1;
+  const int c0 = same ? w : 0;  // first tile of this wave's strip on or above the diagonal
+  const int nst = (g.M + kG64Ant - 1) / kG64Ant;
+  load_stage(0);
+  store_stage();
+  __syncthreads();
+  for (int s2 = 0; s2 < nst; ++s2) {
+    if (s2 + 1 < nst) load_stage((s2 + 1) * kG64Ant);
+#pragma unroll 2  // full unrolling hoists every operand: one wave per SIMD
+    for (int p = 0; p < kG64Ant / 2; ++p) {
+      // k slot q: antenna 2p + slot_m, component comp (Re, Im pairs).
+      const float2 a = Hs[0][16 * w + li][2 * p + slot_m];
+      const double av = comp ? (double)a.y : (double)a.x;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        if (c < c0) continue;  // wave-uniform
+        const float2 h = Hs[opj][16 * c + li][2 * p + slot_m];
+        const double br = comp ? (double)h.y : (double)h.x;
+        const double bim = comp ? -(double)h.x : (double)h.y;
+        accR[c] = mfma64(av, br, accR[c]);
+        accI[c] = mfma64(av, bim, accI[c]);
+      }
+    }
+    __syncthreads();  // every wave is done with this stage
+    if (s2 + 1 < nst) {
+      store_stage();
+      __syncthreads();
+    }
+  }
+
+  // Element (row q + 4r, column li) of tile (w, c) sits in register r. Each
+  // entry strictly above the diagonal of A is written with its conjugate
+  // mirror, the diagonal gets xi and an exactly zero imaginary part, and
+  // entries below the diagonal of a diagonal block are left to their mirror.
+  double2* Ab = g.A64 + (int64_t)b * g.K * g.K;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    if (c < c0) continue;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int gi = bi * kG64Rows + 16 * w + q + 4 * r;
+      const int gj = bj * kG64Rows + 16 * c + li;
+      if (gi >= g.K || gj >= g.K || gi > gj) continue;
+      const double re = accR[c][r], im = accI[c][r];
+      if (gi == gj) {
+        Ab[(int64_t)gi * g.K + gj] = make_double2(re + g.xi, 0.0);
+      } else {
+        Ab[(int64_t)gi * g.K + gj] = make_double2(re, im);
+        Ab[(int64_t)gj * g.K + gi] = make_double2(re, -im);
+      }
     }
   }
 }
@@ -292,8 +342,8 @@ hipError_t launch_fill_synthetic(float2* H, size_t n, uint32_t seed, hipStream_t
 
 hipError_t launch_gram64(const Gram64Launch& g, hipStream_t s) {
   if (g.batch == 0) return hipSuccess;
-  const int nt = (g.K + 15) / 16;
-  hipLaunchKernelGGL(gram64_kernel, dim3(nt * (nt + 1) / 2 * g.batch), dim3(256), 0, s, g);
+  const int nb = (g.K + kG64Rows - 1) / kG64Rows;
+  hipLaunchKernelGGL(gram64_kernel, dim3(nb * (nb + 1) / 2 * g.batch), dim3(256), 0, s, g);
   return hipGetLastError();
 }
 
