@@ -187,21 +187,27 @@ __global__ __launch_bounds__(256) void residual64_kernel(ResidualLaunch r) {
   const double2* Xb = r.X64 + (int64_t)b * K * r.nrhs;
   const int ntr = (K + 15) >> 4;
 
+  // k outermost: the row tiles' products are independent accumulation chains
+  // that share the X operand of each step.
   doublex4 qr[kResMaxRowTiles], qi[kResMaxRowTiles];
 #pragma unroll
   for (int t = 0; t < kResMaxRowTiles; ++t) {
     qr[t] = zero4d();
     qi[t] = zero4d();
-    const int rt = w + 4 * t;
-    if (rt >= ntr) continue;
-    const int ia = rt * 16 + li;  // A-operand row
-    for (int k0 = 0; k0 < K; k0 += 2) {
-      const int kk = k0 + slot_k;
+  }
+  for (int k0 = 0; k0 < K; k0 += 2) {
+    const int kk = k0 + slot_k;
+    const double2 x = (jv && kk < K) ? Xb[(int64_t)j * K + kk] : make_double2(0.0, 0.0);
+    const double xr = comp ? -x.y : x.x, xim = comp ? x.x : x.y;
+#pragma unroll
+    for (int t = 0; t < kResMaxRowTiles; ++t) {
+      const int rt = w + 4 * t;
+      if (rt >= ntr) continue;  // wave-uniform
+      const int ia = rt * 16 + li;  // A-operand row
       const double2 a = (ia < K && kk < K) ? Ab[(int64_t)ia * K + kk] : make_double2(0.0, 0.0);
-      const double2 x = (jv && kk < K) ? Xb[(int64_t)j * K + kk] : make_double2(0.0, 0.0);
       const double av = comp ? a.y : a.x;
-      qr[t] = mfma64(av, comp ? -x.y : x.x, qr[t]);
-      qi[t] = mfma64(av, comp ? x.x : x.y, qi[t]);
+      qr[t] = mfma64(av, xr, qr[t]);
+      qi[t] = mfma64(av, xim, qi[t]);
     }
   }
   // Own rows of the result: rt*16 + q + 4*reg, column j.
