@@ -240,17 +240,17 @@ __global__ __launch_bounds__(256) void gram_bf16_kernel(GramLaunch g) {
   const int ui = ti * 32 + li;
   const bool vi = ui < g.K;
   gptr<const float2> hi = Hb + (int64_t)(vi ? ui : 0) * g.ldh;
-  // Tile t of the panel is (ti, tj0 + t). The diagonal tile reuses the row
-  // block; every other tile has its own column block of users, loaded and split.
-  const bool diag0 = (tj0 == ti);
-  const int nx = ntj - (diag0 ? 1 : 0);  // 0, 1 or 2 column blocks to load
-  const int xoff = diag0 ? 1 : 0;        // tile index of column block q is q + xoff
+  // Tile t of the panel is (ti, tj0 + t); both tiles are always formed, each
+  // from its own column block of users (a diagonal tile loads the row block a
+  // second time; the second tile of a one-tile panel reads zeros and is not
+  // written). Products under a branch, even a workgroup-uniform one, make the
+  // compiler copy the accumulators between register files around each of them.
   bool vx[2];
   gptr<const float2> hx[2];
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
-    const int ux = (tj0 + q + xoff) * 32 + li;
-    vx[q] = (q < nx) && ux < g.K;
+    const int ux = (tj0 + q) * 32 + li;
+    vx[q] = (q < ntj) && ux < g.K;
     hx[q] = Hb + (int64_t)(vx[q] ? ux : 0) * g.ldh;
   }
 
@@ -291,8 +291,7 @@ __global__ __launch_bounds__(256) void gram_bf16_kernel(GramLaunch g) {
     float ri[8], ii[8], rx[2][8], ix[2][8];
     load(hi, vi, m, ri, ii);
 #pragma unroll
-    for (int q = 0; q < 2; ++q)
-      if (q < nx) load(hx[q], vx[q], m, rx[q], ix[q]);
+    for (int q = 0; q < 2; ++q) load(hx[q], vx[q], m, rx[q], ix[q]);
     u32x4 Ar[NS], Ai[NS], An[NS];
     split8<NS>(ri, Ar);
     split8<NS>(ii, Ai);
@@ -300,20 +299,13 @@ __global__ __launch_bounds__(256) void gram_bf16_kernel(GramLaunch g) {
     for (int q = 0; q < NS; ++q)
 #pragma unroll
       for (int e = 0; e < 4; ++e) An[q][e] = neg_bf16x2(Ai[q][e]);
-    if (diag0) {
-      split_mma<NS>(Ar, Ar, accR[0]);
-      split_mma<NS>(Ai, Ai, accR[0]);
-      split_mma<NS>(Ar, Ai, accI[0]);
-      split_mma<NS>(An, Ar, accI[0]);
-    }
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
-      if (q >= nx) break;
       u32x4 Xr[NS], Xi[NS];
       split8<NS>(rx[q], Xr);
       split8<NS>(ix[q], Xi);
-      floatx16& aR = accR[q + xoff];
-      floatx16& aI = accI[q + xoff];
+      floatx16& aR = accR[q];
+      floatx16& aI = accI[q];
       split_mma<NS>(Ar, Xr, aR);
       split_mma<NS>(Ai, Xi, aR);
       split_mma<NS>(Ar, Xi, aI);

@@ -33,8 +33,8 @@ __device__ __forceinline__ void upper_tile16(int t, int nt, int& ti, int& tj) {
 
 // One workgroup per (instance, 64 x 64 block of the upper block triangle of A).
 // Wave w owns block rows 16w .. 16w+15 against all 64 block columns (four
-// 16 x 16 tiles, so no reduction across waves); in a diagonal block it skips
-// the tiles that lie wholly below the diagonal. The channel rows of the block
+// 16 x 16 tiles, so no reduction across waves); in a diagonal block the tiles
+// wholly below the diagonal are formed and discarded. The channel rows of the block
 // pass through LDS 16 antennas at a time, read from global memory with
 // coalesced 16-byte loads one stage ahead (into registers) of the products.
 constexpr int kG64Rows = 64;  // block edge
@@ -114,7 +114,7 @@ __global__ __launch_bounds__(256) void gram64_kernel(Gram64Launch g) {
     accI[c] = zero4d();
   }
   const int opj = same ? 0 : 1;
-  const int c0 = same ? w : 0;  // first tile of this wave's strip on or above the diagonal
+  const int c0 = same ? w : 0;  // first tile of this wave's strip on or above the diagonal (the rest is discarded)
   const int nst = (g.M + kG64Ant - 1) / kG64Ant;
   load_stage(0);
   store_stage();
@@ -126,9 +126,11 @@ __global__ __launch_bounds__(256) void gram64_kernel(Gram64Launch g) {
       // k slot q: antenna 2p + slot_m, component comp (Re, Im pairs).
       const float2 a = Hs[0][16 * w + li][2 * p + slot_m];
       const double av = comp ? (double)a.y : (double)a.x;
+      // Every wave forms all four tiles: a per-tile branch here, though
+      // wave-uniform, made the compiler copy the accumulators out of and back
+      // into the matrix-core registers around each product and wait for it.
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
-        if (c < c0) continue;  // wave-uniform
         const float2 h = Hs[opj][16 * c + li][2 * p + slot_m];
         const double br = comp ? (double)h.y : (double)h.x;
         const double bim = comp ? -(double)h.x : (double)h.y;
