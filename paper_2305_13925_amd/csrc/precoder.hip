@@ -191,20 +191,22 @@ __device__ __forceinline__ int nth_active(unsigned act, int n) {
   return last;
 }
 
-// VR: visibility-region sparse variant (one 128-antenna block per workgroup):
+// VR: visibility-region sparse variant (one antenna block per workgroup):
 // only the user steps whose 32-user block has a span reaching this block's
 // antennas are computed (the others hold zero channel entries here).
-template <int NS, int KT, int NJ, bool FULL, bool VR>
-__global__ __launch_bounds__(256) void precoder_bf16_kernel(PrecoderLaunch e) {
+// NW waves per workgroup, one 32-antenna tile each: blocks of 32 NW antennas.
+template <int NS, int KT, int NJ, bool FULL, bool VR, int NW>
+__global__ __launch_bounds__(64 * NW) void precoder_bf16_kernel(PrecoderLaunch e) {
+  constexpr int BLK = 32 * NW;
   constexpr int KP = KT * 32;
   constexpr int K8 = KP / 8;  // groups of 8 users (one lane half of one step)
   constexpr int NC = 32 * NJ;
   const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int jl = lane & 31, half = lane >> 5;
-  // A workgroup covers `mt` consecutive blocks of 128 antennas (one 32-antenna
+  // A workgroup covers `mt` consecutive blocks of BLK antennas (one 32-antenna
   // tile per wave and block), so its split of beta_pow X is reused mt times.
   const int mt = e.mtiles;
-  const int nblk = (e.M + 127) / 128;
+  const int nblk = (e.M + BLK - 1) / BLK;
   const int nmb = (nblk + mt - 1) / mt;
   const int ncw = (e.nrhs + NC - 1) / NC;
   const int per = nmb * ncw;
@@ -233,7 +235,7 @@ __global__ __launch_bounds__(256) void precoder_bf16_kernel(PrecoderLaunch e) {
   unsigned act = (S >= 32) ? ~0u : ((1u << S) - 1u);
   int nact = S;
   if constexpr (VR) {
-    const int m_lo = blk0 * 128, m_hi = min(e.M, m_lo + 128);
+    const int m_lo = blk0 * BLK, m_hi = min(e.M, m_lo + BLK);
     act = 0;
     for (int c = 0; c < KT; ++c) {
       const int2 sp = e.tile_span[(int64_t)b * KT + c];
@@ -255,7 +257,7 @@ __global__ __launch_bounds__(256) void precoder_bf16_kernel(PrecoderLaunch e) {
         st = S - 1;
       }
     }
-    const int mrow = blk * 128 + w * 32 + jl;
+    const int mrow = blk * BLK + w * 32 + jl;
     const bool v = FULL || mrow < e.M;
     gptr<const float2> hc = Hb + (v ? mrow : 0);
     const int k8 = 2 * st + half;
@@ -280,7 +282,7 @@ __global__ __launch_bounds__(256) void precoder_bf16_kernel(PrecoderLaunch e) {
   }
 
   gptr<const float2> Xb = as_global(e.X + (int64_t)b * e.stride_x);
-  for (int idx = threadIdx.x; idx < K8 * NC; idx += 256) {
+  for (int idx = threadIdx.x; idx < K8 * NC; idx += 64 * NW) {
     const int jj = idx % NC, k8 = idx / NC;
     if (VR && !((act >> (k8 >> 1)) & 1u)) continue;  // a user step this block never reads
     const int j = cw * NC + jj;
@@ -354,7 +356,7 @@ __global__ __launch_bounds__(256) void precoder_bf16_kernel(PrecoderLaunch e) {
         compute(hrB, hiB, st + 1, gs + 3);
       }
     }
-    const int m = blk * 128 + w * 32 + jl;
+    const int m = blk * BLK + w * 32 + jl;
     if (FULL || m < e.M) {
       gptr<float2> Wb = Wbase + m;
 #pragma unroll
@@ -371,9 +373,14 @@ __global__ __launch_bounds__(256) void precoder_bf16_kernel(PrecoderLaunch e) {
 
 template <int NS, int KT, int NJ>
 hipError_t launch_bf16_nj(const PrecoderLaunch& e, hipStream_t s) {
-  const int nblk = (e.M + 127) / 128;
+  // Beyond K = 128 the split of beta_pow X (2 NS K/8 32 NJ 16-byte entries)
+  // leaves room for one workgroup per compute unit, so the workgroup has 8
+  // waves (two per SIMD) sharing it, over blocks of 256 antennas.
+  constexpr int NW = KT > 4 ? 8 : 4;
+  constexpr int BLK = 32 * NW;
+  const int nblk = (e.M + BLK - 1) / BLK;
   PrecoderLaunch p = e;
-  // Blocks of 128 antennas per workgroup: enough to amortise the split of X,
+  // Blocks of BLK antennas per workgroup: enough to amortise the split of X,
   // few enough to keep several workgroups per compute unit busy. The sparse
   // variant takes one block per workgroup (its user steps depend on it).
   const bool vr = e.tile_span != nullptr && KT > 2;
@@ -385,12 +392,12 @@ hipError_t launch_bf16_nj(const PrecoderLaunch& e, hipStream_t s) {
   const int nmb = (nblk + p.mtiles - 1) / p.mtiles;
   const size_t lds = (size_t)2 * NS * (KT * 4) * 32 * NJ * 16;
   // FULL: every user, antenna and column of every tile is in range (no masks).
-  const bool full = (e.K == KT * 32) && (e.M % 128 == 0) && (e.nrhs % (32 * NJ) == 0);
+  const bool full = (e.K == KT * 32) && (e.M % BLK == 0) && (e.nrhs % (32 * NJ) == 0);
   const int grid = e.batch * nmb * ((e.nrhs + 32 * NJ - 1) / (32 * NJ));
-  auto k = full ? (vr ? precoder_bf16_kernel<NS, KT, NJ, true, true> : precoder_bf16_kernel<NS, KT, NJ, true, false>)
-                : (vr ? precoder_bf16_kernel<NS, KT, NJ, false, true> : precoder_bf16_kernel<NS, KT, NJ, false, false>);
+  auto k = full ? (vr ? precoder_bf16_kernel<NS, KT, NJ, true, true, NW> : precoder_bf16_kernel<NS, KT, NJ, true, false, NW>)
+                : (vr ? precoder_bf16_kernel<NS, KT, NJ, false, true, NW> : precoder_bf16_kernel<NS, KT, NJ, false, false, NW>);
   if (lds > 65536) (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL(k, dim3(grid), dim3(256), lds, s, p);
+  hipLaunchKernelGGL(k, dim3(grid), dim3(64 * NW), lds, s, p);
   return hipGetLastError();
 }
 
