@@ -93,7 +93,7 @@ struct PrecoderLaunch {
   const double* fpart64; int ncb64;         // nullable: FP64 ||H X||^2 partials (refined path)
   int no_vec;                               // 1: some precoder pointer or ldw does not allow 16-byte stores
   int nj;                                   // column tiles per wave: 0 = default rule, 1 or 2 = tuned choice
-  int mtiles;                               // split-BF16: 128-antenna blocks per workgroup (0 = default rule)
+  int mtiles;                               // split-BF16: antenna blocks (128, or 256 beyond K = 128) per workgroup (0 = default rule)
   const int2* tile_span;                    // nullable (split-BF16, K > 64): user-block antenna spans; user
                                             // blocks whose span misses a workgroup's antennas are skipped
   const int32_t* wg_status;                 // nullable: the solver's per-workgroup statuses (ncb per instance),
