@@ -367,3 +367,28 @@ def test_refined_full_size_precision_sampled(torch, sess):
     for b in (0, 97, 255):
         Xs, _, _ = oracle.direct_rzf(H[b].T.astype(np.complex128), xi)
         assert rel(Xn[b].T, Xs) <= REFINE_TOL
+
+
+@pytest.mark.parametrize("prec", [bd.GRAM_FP32, bd.GRAM_BF16X6])
+@pytest.mark.parametrize("M,K", [(333, 100), (344, 100), (333, 200), (37, 40)])
+def test_refined_ragged_shapes(torch, sess, prec, M, K):
+    # The FP64 Gram works in 64 x 64 blocks of A and stages 16 antennas at a
+    # time: K off a multiple of 64 leaves rows past K in the last block, and M
+    # off a multiple of 16 leaves a partial last stage (and rows of H whose
+    # length is not a multiple of two complex entries). The refined result must
+    # still reach the FP64 direct precoder.
+    rng = np.random.default_rng(K + M)
+    n, xi = 2, K / 10.0
+    H = chan(rng, n, K, M)
+    X64 = torch.empty((n, K, K), dtype=torch.complex128, device="cuda")
+    W, st, rc = bd.rzf_precoder(sess, dev(torch, H), xi, tol=1e-6, max_iter=200, precision=prec | bd.REFINE_FP64,
+                                refine_tol=REFINE_TOL, X64_out=X64, stats=True)
+    assert rc == bd.OK, st
+    assert st["max_refine_residual"] <= REFINE_TOL
+    Xn, Wn = X64.cpu().numpy(), W.cpu().numpy()
+    for b in range(n):
+        Xs, Ws, _ = oracle.direct_rzf(H[b].T.astype(np.complex128), xi)
+        ex, ew = rel(Xn[b].T, Xs), rel(Wn[b].T, Ws)
+        print(f"refined ragged M={M} K={K} prec={prec} b={b}: steps {st['refine_steps']} X64 err {ex:.2e} W err {ew:.2e}")
+        assert ex <= REFINE_TOL
+        assert ew <= 1e-6
