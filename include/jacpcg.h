@@ -343,7 +343,9 @@ typedef struct {
  * in FIFO order while its HBM budget (H + W + workspace of the admitted
  * requests) and in-flight batch slots allow, batches admitted requests of the
  * same shape and settings into one launch, and runs batches of different slots
- * concurrently. A request's result does not depend on what it is batched with.
+ * concurrently. There is one slot per hardware queue of the process
+ * (GPU_MAX_HW_QUEUES, 4 by default, at most 8), each with its own stream. A
+ * request's result does not depend on what it is batched with.
  * Errors: E_INVALID_ARG (sizes, NULL buffers, xi < 0, power <= 0, tol < 0,
  * max_iter < 0, unknown flags), E_UNSUPPORTED (refinement requested),
  * E_BUDGET (the request alone needs more than the session budget), E_HIP (the

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <unordered_set>
 
@@ -15,10 +16,18 @@ namespace jacpcg {
 
 namespace {
 
-// One slot per hardware queue of the process (HIP's default is 4): a fifth
-// stream would share an in-order hardware queue with the first, so a small
-// batch could wait behind a large one's kernels instead of running beside them.
-constexpr int kSlots = 4;
+// One slot per hardware queue of the process (GPU_MAX_HW_QUEUES, HIP's
+// default 4; at most 8 slots): one more stream would share an in-order
+// hardware queue with the first, so a small batch could wait behind a large
+// one's kernels instead of running beside them.
+int slot_count() {
+  int n = 4;
+  if (const char* v = std::getenv("GPU_MAX_HW_QUEUES")) {
+    const int q = std::atoi(v);
+    if (q > 0) n = q;
+  }
+  return std::min(8, std::max(1, n));
+}
 
 uint64_t mix(uint64_t h, uint64_t v) {
   h ^= v + 0x9e3779b97f4a7c15ULL + (h << 6) + (h >> 2);
@@ -43,7 +52,7 @@ double Scheduler::now_us() const {
 
 void Scheduler::start() {
   if (running_) return;
-  slots_.resize(kSlots);
+  slots_.resize(slot_count());
   for (auto& sl : slots_) {
     (void)hipSetDevice(s_->device);
     (void)hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
