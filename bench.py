@@ -395,29 +395,44 @@ def next_rows(bd, torch, sess, H, xi, stream, samples, reps=20):
     X64 = torch.empty((wp.batch, wp.K, wp.K), dtype=torch.complex128, device="cuda")
     picks = (0, wp.batch - 1)
     Hpick = {b: Hp[b].cpu().numpy() for b in picks}
-    for label, gp in (("precision_refined", bd.GRAM_FP32), ("precision_refined_bf16x3", bd.GRAM_BF16X3)):
-        # before refinement: the FP32-PCG precoder of this Gram
+    # Before refinement: the FP32-PCG precoder of each Gram precision. With
+    # refinement the solves take the FP64 Gram rounded to FP32, so one refined
+    # row covers every Gram precision.
+    label = "precision_refined"
+    out[label] = {"before_refinement": {}}
+    for name, gp in (("fp32_gram", bd.GRAM_FP32), ("bf16x3_gram", bd.GRAM_BF16X3)):
         bd.rzf_precoder(sess, Hp, 12.8, tol=1e-6, max_iter=64, precision=gp, W=Wp, stream=stream)
         torch.cuda.synchronize()
-        pre = {b: Wp[b].cpu().numpy().T for b in picks}
-        run = lambda: bd.rzf_precoder(sess, Hp, 12.8, tol=1e-6, max_iter=64, precision=gp | bd.REFINE_FP64,
-                                      W=Wp, X64_out=X64, stats=True, stream=stream)
-        run()
-        t0 = time.perf_counter()
-        for _ in range(3):
-            _, pst, _ = run()
-        ms_p = (time.perf_counter() - t0) * 1e3 / 3
+        out[label]["before_refinement"][name] = {}
         for b in picks:
-            samples.append(dict(path=(label,), H=Hpick[b], xi=12.8, T=None, checks=[
-                ("sampled_err_W_vs_fp64_before_refinement", "W_fp64", pre[b]),
-                ("sampled_err_X64_vs_fp64", "X_fp64", X64[b].cpu().numpy().T),
+            samples.append(dict(path=(label, "before_refinement", name), H=Hpick[b], xi=12.8, T=None, checks=[
                 ("sampled_err_W_vs_fp64", "W_fp64", Wp[b].cpu().numpy().T)]))
-        out[label] = {"ms": round(ms_p, 3), "precoders_per_s": round(wp.batch / (ms_p / 1e3), 1),
-                      "max_iters": pst["max_iters"], "refine_steps": pst["refine_steps"],
-                      "max_refine_residual": pst["max_refine_residual"],
-                      "config": "256 x (M=4096 = 16 x 256, K=128), r=0.7, regions of 6-12, xi=12.8, "
-                                + ("FP32" if gp == bd.GRAM_FP32 else "split-BF16 (two parts)")
-                                + " Gram, FP32 PCG to 1e-6 + FP64 refinement to 1e-10 (host-synchronised)"}
+    run = lambda: bd.rzf_precoder(sess, Hp, 12.8, tol=1e-6, max_iter=64, precision=bd.GRAM_FP32 | bd.REFINE_FP64,
+                                  W=Wp, X64_out=X64, stats=True, stream=stream)
+    run()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        _, pst, _ = run()
+    ms_p = (time.perf_counter() - t0) * 1e3 / 3
+    # per-phase kernel times from separate profiled calls (the event bookkeeping
+    # can add host time to this host-synchronised path)
+    sess.phase_times(reset=True)
+    sess.set_profiling(True)
+    for _ in range(3):
+        run()
+    sess.set_profiling(False)
+    ph = sess.phase_times(reset=True)
+    for b in picks:
+        samples.append(dict(path=(label,), H=Hpick[b], xi=12.8, T=None, checks=[
+            ("sampled_err_X64_vs_fp64", "X_fp64", X64[b].cpu().numpy().T),
+            ("sampled_err_W_vs_fp64", "W_fp64", Wp[b].cpu().numpy().T)]))
+    out[label].update({
+        "ms": round(ms_p, 3), "precoders_per_s": round(wp.batch / (ms_p / 1e3), 1),
+        "max_iters": pst["max_iters"], "refine_steps": pst["refine_steps"],
+        "max_refine_residual": pst["max_refine_residual"],
+        "phases_ms": {k: round(v[0] / 3, 3) for k, v in ph.items() if v[1]},
+        "config": "256 x (M=4096 = 16 x 256, K=128), r=0.7, regions of 6-12, xi=12.8, FP32 PCG to 1e-6 on the "
+                  "FP64 Gram rounded to FP32, + FP64 refinement to 1e-10 (host-synchronised)"})
     del Hp, Wp, X64
 
     # Jacobi-PCG vs plain CG on the gain-normalised channels at 20 dB, where

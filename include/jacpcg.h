@@ -198,7 +198,9 @@ typedef struct {
  * W: column-major M x K per instance (precoding vector g_k contiguous).
  * precision | JACPCG_REFINE_FP64: after the FP32 solve, X is refined in FP64
  *   (R = I - A64 X64 in FP64 with A64 the FP64 Gram, FP32 PCG on the
- *   correction) until ||R||_F / ||I||_F <= refine_tol or 16 steps.
+ *   correction) until ||R||_F / ||I||_F <= refine_tol or 16 steps. The FP32
+ *   solves then use A64 rounded to FP32 as their matrix, so the Gram
+ *   precision bits do not apply.
  * X_out (nullable): column-major K x K c64 copy of X per instance (ld K,
  *   stride K*K). X64_out (nullable): the same in c128 (refined path; the FP32
  *   solution widened otherwise). flags: as jacpcg_solve.

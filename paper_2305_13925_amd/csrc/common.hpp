@@ -155,6 +155,8 @@ size_t pcg_state_floats_per_wg(int K);
 hipError_t launch_status_reduce(const int32_t* wg_status, int ncb, int batch, int32_t* status, hipStream_t s);
 hipError_t launch_precoder(const PrecoderLaunch& e, hipStream_t s);
 hipError_t launch_gram64(const Gram64Launch& g, hipStream_t s);
+hipError_t launch_narrow_gram(const double2* A64, int K, int batch, double xi, float2* A, int64_t lda,
+                              int64_t stride_a, float* gdiag, hipStream_t s);
 hipError_t launch_residual(const ResidualLaunch& r, hipStream_t s);
 hipError_t launch_accumulate(const AccumulateLaunch& a, hipStream_t s);
 int residual_workgroups_per_instance(int nrhs);

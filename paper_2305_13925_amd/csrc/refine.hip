@@ -275,6 +275,20 @@ __global__ __launch_bounds__(256) void residual64_kernel(ResidualLaunch r) {
   }
 }
 
+// The FP32 system matrix of the refined path: A64 rounded once to FP32 (more
+// accurate than any FP32-accumulated Gram), and diag(H^H H) = Re A64_ii - xi
+// for the solver's power partials.
+__global__ void narrow_gram_kernel(const double2* __restrict__ A64, int K, double xi, float2* __restrict__ A,
+                                   int64_t lda, int64_t stride_a, float* __restrict__ gdiag) {
+  const int b = blockIdx.y;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= K * K) return;
+  const int i = idx / K, j = idx - i * K;
+  const double2 v = A64[(int64_t)b * K * K + idx];
+  A[(int64_t)b * stride_a + (int64_t)i * lda + j] = make_float2((float)v.x, (float)v.y);
+  if (i == j && gdiag) gdiag[(int64_t)b * K + i] = (float)(v.x - xi);
+}
+
 __global__ void accumulate_kernel(AccumulateLaunch a) {
   const int b = blockIdx.y;
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
@@ -352,6 +366,14 @@ hipError_t launch_gram64(const Gram64Launch& g, hipStream_t s) {
   if (g.batch == 0) return hipSuccess;
   const int nb = (g.K + kG64Rows - 1) / kG64Rows;
   hipLaunchKernelGGL(gram64_kernel, dim3(nb * (nb + 1) / 2 * g.batch), dim3(256), 0, s, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_narrow_gram(const double2* A64, int K, int batch, double xi, float2* A, int64_t lda,
+                              int64_t stride_a, float* gdiag, hipStream_t s) {
+  if (batch == 0) return hipSuccess;
+  const dim3 grid((unsigned)((K * K + 255) / 256), (unsigned)batch);
+  hipLaunchKernelGGL(narrow_gram_kernel, grid, dim3(256), 0, s, A64, K, xi, A, lda, stride_a, gdiag);
   return hipGetLastError();
 }
 

@@ -228,24 +228,35 @@ int jacpcg_session::run_rzf(hipStream_t st, int batch, int M, int K, const float
       hipError_t es = launch_spans(sl, q);
       if (es != hipSuccess) return es;
     }
-    GramLaunch g{};
-    g.H = H;
-    g.ldh = ldh;
-    g.stride_h = stride_h;
-    g.batch = batch;
-    g.M = M;
-    g.K = K;
-    g.xi = (float)xi;
-    g.A = A;
-    g.lda = K;
-    g.stride_a = (int64_t)KK;
-    g.diag = nullptr;
-    g.gdiag = gdiag;
-    g.precision = gram_prec;
-    g.m_split = tuner.gram_waves(M, K, gram_prec);
-    g.tile_span = tspan;
-    hipError_t e = run(JACPCG_PHASE_GRAM, [&] { return launch_gram(g, q); });
-    if (e != hipSuccess) return e;
+    hipError_t e = hipSuccess;
+    if (refine) {
+      // The refinement needs the FP64 Gram anyway: the FP32 solves take it
+      // rounded once to FP32 (the Gram precision bits do not apply).
+      Gram64Launch g64{H, ldh, stride_h, batch, M, K, xi, at<double2>(oA64)};
+      e = run(JACPCG_PHASE_GRAM64, [&] { return launch_gram64(g64, q); });
+      if (e != hipSuccess) return e;
+      e = launch_narrow_gram(at<double2>(oA64), K, batch, xi, A, K, (int64_t)KK, gdiag, q);
+      if (e != hipSuccess) return e;
+    } else {
+      GramLaunch g{};
+      g.H = H;
+      g.ldh = ldh;
+      g.stride_h = stride_h;
+      g.batch = batch;
+      g.M = M;
+      g.K = K;
+      g.xi = (float)xi;
+      g.A = A;
+      g.lda = K;
+      g.stride_a = (int64_t)KK;
+      g.diag = nullptr;
+      g.gdiag = gdiag;
+      g.precision = gram_prec;
+      g.m_split = tuner.gram_waves(M, K, gram_prec);
+      g.tile_span = tspan;
+      e = run(JACPCG_PHASE_GRAM, [&] { return launch_gram(g, q); });
+      if (e != hipSuccess) return e;
+    }
 
     PcgLaunch p{};
     p.A = A;
@@ -363,11 +374,9 @@ int jacpcg_session::run_rzf(hipStream_t st, int batch, int M, int K, const float
     float2* E32 = at<float2>(oE32);
     double* scale = at<double>(oSc);
     double* rn2 = at<double>(oRn);
-    Gram64Launch g64{H, ldh, stride_h, batch, M, K, xi, A64};
-    hipError_t e = timed(st, JACPCG_PHASE_GRAM64, [&] { return launch_gram64(g64, st); });
-    if (e != hipSuccess) return hip_error(this, e, "gram64 launch");
+    // A64 was formed before the first solve.
     AccumulateLaunch acc{X64, X, nullptr, batch, K, K, 1, nullptr};
-    e = launch_accumulate(acc, st);  // X64 = X (exact widening)
+    hipError_t e = launch_accumulate(acc, st);  // X64 = X (exact widening)
     if (e != hipSuccess) return hip_error(this, e, "accumulate launch");
     double* h_rn = (double*)host_scratch((size_t)batch * n16 * sizeof(double));
     if (!h_rn) return set_error(JACPCG_E_OUT_OF_MEMORY, "pinned host staging allocation failed");
