@@ -57,7 +57,7 @@ PEAK_BF16_MFMA_TFLOPS = 2500.0    # MI355X dense BF16 matrix peak
 
 def algorithmic(M, K, n, T, batch, gram, epilogue, T_exec=None):
     """Per launch: algorithmic flops and HBM bytes of each kernel, and the work
-    its instructions actually execute on the matrix cores (see DESIGN.md).
+    its instructions actually execute on the matrix cores.
 
     T is the mean number of solver iterations per column (useful work);
     T_exec (default T) the mean over 32-column blocks of the block's largest
@@ -472,7 +472,7 @@ def main():
         return calibrate_copy()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {a.gpus}): instances are independent and a "
-              "multi-GPU run would shard them without communication; see DESIGN.md.", file=sys.stderr)
+              "multi-GPU run would shard them without communication.", file=sys.stderr)
         return 2
     import torch
     from channelgen import workload, channel_batch
