@@ -29,11 +29,6 @@ int slot_count() {
   return std::min(8, std::max(1, n));
 }
 
-uint64_t mix(uint64_t h, uint64_t v) {
-  h ^= v + 0x9e3779b97f4a7c15ULL + (h << 6) + (h >> 2);
-  return h;
-}
-
 uint64_t bits(double d) {
   uint64_t u;
   std::memcpy(&u, &d, sizeof u);
@@ -131,16 +126,14 @@ int Scheduler::submit(const jacpcg_request& r, uint64_t* ticket) {
   Req q;
   q.r = r;
   q.bytes = bytes;
-  uint64_t k = 0;
-  k = mix(k, (uint64_t)r.M);
-  k = mix(k, (uint64_t)r.K);
-  k = mix(k, (uint64_t)r.precision);
-  k = mix(k, (uint64_t)r.flags);
-  k = mix(k, (uint64_t)r.max_iter);
-  k = mix(k, bits(r.tol));
-  k = mix(k, bits(r.xi));
-  k = mix(k, bits(r.power));
-  q.key = k;
+  q.key.M = r.M;
+  q.key.K = r.K;
+  q.key.precision = r.precision;
+  q.key.flags = r.flags;
+  q.key.max_iter = r.max_iter;
+  q.key.tol_bits = bits(r.tol);
+  q.key.xi_bits = bits(r.xi);
+  q.key.power_bits = bits(r.power);
   // The request's device work will wait for what is queued on its stream now
   // (the production of H).
   q.ready = take_event();

@@ -43,7 +43,7 @@ class Scheduler {
   struct Req {
     jacpcg_request r;
     size_t bytes = 0;
-    uint64_t key = 0;
+    BatchKey key;
     int state = kQueued;
     int status = JACPCG_NOT_READY;
     int max_iters = 0;

@@ -9,10 +9,24 @@
 
 namespace jacpcg {
 
+// What requests must share to run as one batch: the shape and every solve
+// setting, compared field by field (floating-point settings by their bits, so
+// two requests batch together only when the kernels would see identical
+// arguments).
+struct BatchKey {
+  int M = 0, K = 0, precision = 0, flags = 0, max_iter = 0;
+  uint64_t tol_bits = 0, xi_bits = 0, power_bits = 0;
+  bool operator==(const BatchKey& o) const {
+    return M == o.M && K == o.K && precision == o.precision && flags == o.flags && max_iter == o.max_iter &&
+           tol_bits == o.tol_bits && xi_bits == o.xi_bits && power_bits == o.power_bits;
+  }
+  bool operator!=(const BatchKey& o) const { return !(*this == o); }
+};
+
 struct PendingReq {
   uint64_t ticket;
   size_t bytes;
-  uint64_t key;
+  BatchKey key;
 };
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -63,11 +77,12 @@ inline size_t admit_prefix(const std::vector<PendingReq>& queue, size_t used, si
   return n;
 }
 
-// Admitted requests grouped by key (shape and solve settings); groups ordered
-// by their first request, requests in arrival order inside a group.
+// Admitted requests grouped by key (shape and solve settings, every field
+// equal); groups ordered by their first request, requests in arrival order
+// inside a group.
 inline std::vector<std::vector<size_t>> group_by_key(const std::vector<PendingReq>& admitted) {
   std::vector<std::vector<size_t>> groups;
-  std::vector<uint64_t> keys;
+  std::vector<BatchKey> keys;
   for (size_t i = 0; i < admitted.size(); ++i) {
     size_t g = 0;
     while (g < keys.size() && keys[g] != admitted[i].key) ++g;

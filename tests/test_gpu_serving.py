@@ -133,3 +133,27 @@ def test_request_waits_for_the_stream_that_produces_H(torch, sess):
     W_dir = bd.rzf_precoder(sess, H, 6.4, tol=0.0, max_iter=8)
     torch.cuda.synchronize()
     assert torch.equal(W, W_dir)
+
+
+def test_requests_differing_in_one_setting_never_share_a_batch(torch, sess):
+    # Requests queued together are grouped into one batch only when shape and
+    # every solve setting match. These pairs differ in M alone (42 / 43 at
+    # K = 59) and in max_iter alone (468 / 502): each must come out exactly as
+    # its own direct call. Long requests occupy the slots first, so the pairs
+    # wait in the queue and are admitted in one pass.
+    blockers = [device_pool(4096, 4, 256, 0.5, (2, 4), 32, 40 + i) for i in range(4)]
+    bouts = [torch.empty_like(h) for h in blockers]
+    cases = [(42, 59, 16, 3), (43, 59, 16, 3), (4096, 8, 468, 2), (4096, 8, 502, 2)]
+    Hs, Ws = [], []
+    for i, (M, K, _, n) in enumerate(cases):
+        Hs.append(device_pool(M, 1, K, 0.5, (1, 1), n, 60 + i))
+        Ws.append(torch.empty_like(Hs[-1]))
+    torch.cuda.synchronize()
+    tb = [bd.jacpcg_submit(sess, h, w, 25.6, tol=0.0, max_iter=64) for h, w in zip(blockers, bouts)]
+    tickets = [bd.jacpcg_submit(sess, H, W, 1.6, tol=1e-6, max_iter=mi) for H, W, (_, _, mi, _) in zip(Hs, Ws, cases)]
+    for t in tb + tickets:
+        assert bd.jacpcg_wait(sess, t, 60000)["status"] in (bd.OK, bd.NOT_CONVERGED)
+    for H, W, (M, K, mi, _) in zip(Hs, Ws, cases):
+        W_dir = bd.rzf_precoder(sess, H, 1.6, tol=1e-6, max_iter=mi)
+        torch.cuda.synchronize()
+        assert torch.equal(W, W_dir), (M, K, mi)
