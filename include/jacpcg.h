@@ -219,6 +219,33 @@ int rzf_precoder(jacpcg_session* s, void* stream, int batch, int M, int K,
                  jacpcg_c64* W, int64_t ldw, int64_t stride_w,
                  jacpcg_c64* X_out, jacpcg_c128* X64_out, jacpcg_stats* stats);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops or harnesses that forbid hipMalloc): rzf_precoder
+ * without refinement, stats, X_out or X64_out, whose workspace (A, diag(H^H H),
+ * X, the solver's per-workgroup partials) lives in a fixed device array of the
+ * library instead of the session's arena. The call allocates nothing: no
+ * hipMalloc, hipFree or allocating library routine, and it records no event.
+ * The array holds 96 MiB on each device the library runs on, from the first
+ * session on that device until the process ends; a batch needs
+ *   2 * batch * K * K * 8 + batch * K * 4 + 2 * batch * ceil(K/32) * 4 bytes
+ * (each of the five buffers rounded up to 256 bytes): up to 1529 instances
+ * at K = 64, 383 at K = 128, 95 at K = 256.
+ * Every call on one device shares that device's array, which keeps the last
+ * call's contents: calls that overlap on one device (other streams, other
+ * sessions, other threads) race and give undefined results; the caller orders
+ * them. Nothing in the array needs to start at zero.
+ * status (device, nullable): batch int32, the per-instance status of
+ * jacpcg_solve (OK / NOT_CONVERGED / E_BREAKDOWN).
+ * Asynchronous on `stream`; outputs valid after it is synchronised.
+ * Every other argument as rzf_precoder.
+ * Errors: as rzf_precoder; E_INVALID_ARG when the batch does not fit the
+ * array (the message gives both sizes); E_UNSUPPORTED for JACPCG_REFINE_FP64;
+ * E_HIP if the array's device address could not be looked up. */
+int rzf_precoder_noalloc(jacpcg_session* s, void* stream, int batch, int M, int K,
+                         const jacpcg_c64* H, int64_t ldh, int64_t stride_h,
+                         double xi, double power, double tol, int max_iter, int precision, int flags,
+                         jacpcg_c64* W, int64_t ldw, int64_t stride_w, int32_t* status);
+
 /* The same result computed the plain way, one instance at a time: per instance
  * one Gram launch, one launch per PCG iteration (with a host-side convergence
  * check after each when tol > 0), then the precoder launch. The baseline the

@@ -106,6 +106,8 @@ def _declare(lib):
     lib.rzf_precoder.argtypes = [_vp, _vp, C.c_int, C.c_int, C.c_int, _vp, _i64, _i64, C.c_double, C.c_double,
                                  C.c_double, C.c_int, C.c_int, C.c_int, C.c_double, _vp, _i64, _i64, _vp, _vp,
                                  C.POINTER(JacpcgStats)]
+    lib.rzf_precoder_noalloc.argtypes = [_vp, _vp, C.c_int, C.c_int, C.c_int, _vp, _i64, _i64, C.c_double,
+                                         C.c_double, C.c_double, C.c_int, C.c_int, C.c_int, _vp, _i64, _i64, _vp]
     lib.rzf_precoder_plain.argtypes = [_vp, _vp, C.c_int, C.c_int, C.c_int, _vp, _i64, _i64, C.c_double,
                                        C.c_double, C.c_double, C.c_int, C.c_int, _vp, _i64, _i64, _vp,
                                        C.POINTER(JacpcgStats)]
@@ -129,7 +131,7 @@ def _declare(lib):
     lib.jacpcg_session_clock_us.argtypes = [_vp]
     lib.jacpcg_session_clock_us.restype = C.c_double
     for name in ("jacpcg_session_create", "jacpcg_session_set_profiling", "jacpcg_session_phase_times",
-                 "jacpcg_gram", "jacpcg_solve", "rzf_precoder", "rzf_precoder_plain", "rzf_transmit", "rzf_sinr",
+                 "jacpcg_gram", "jacpcg_solve", "rzf_precoder", "rzf_precoder_noalloc", "rzf_precoder_plain", "rzf_transmit", "rzf_sinr",
                  "rzf_block_precoder", "rzf_precoder_vr", "jacpcg_submit", "jacpcg_session_set_graphs",
                  "jacpcg_autotune",
                  "jacpcg_poll", "jacpcg_wait", "jacpcg_cancel"):
@@ -309,6 +311,25 @@ def rzf_precoder(session, H, xi, power=1.0, tol=0.0, max_iter=16, precision=GRAM
                                    C.byref(st) if st is not None else None))
     if stats:
         return W, st.as_dict(), rc
+    return W
+
+
+def rzf_precoder_noalloc(session, H, xi, power=1.0, tol=0.0, max_iter=16, precision=GRAM_FP32,
+                         flags=PRECOND_JACOBI, W=None, status=None, stream=None):
+    """rzf_precoder on the library's fixed device workspace (allocates nothing
+    in the call; calls overlapping on one GPU race). H complex64 [batch, K, M]
+    -> W [batch, K, M]; status: optional int32 [batch] device tensor."""
+    torch = _torch()
+    _require(H, "H", torch.complex64)
+    batch, K, M = H.shape
+    if W is None:
+        W = torch.empty((batch, K, M), dtype=torch.complex64, device=H.device)
+    _require(W, "W", torch.complex64, (batch, K, M))
+    if status is not None:
+        _require(status, "status", torch.int32, (batch,))
+    _check(lib().rzf_precoder_noalloc(session.handle, _stream(stream), batch, M, K, _ptr(H), M, K * M, float(xi),
+                                      float(power), float(tol), int(max_iter), int(precision), int(flags), _ptr(W),
+                                      M, K * M, _ptr(status)))
     return W
 
 

@@ -160,6 +160,9 @@ int jacpcg_session_create(int device, size_t hbm_budget_bytes, const char* tune_
   s->budget = hbm_budget_bytes;
   if (tune_cache_path) s->tune_path = tune_cache_path;
   s->tuner.load(s->tune_path);
+  // Device address of the fixed scratch array of rzf_precoder_noalloc; a
+  // failure is reported by that entry point, not here.
+  (void)noalloc_setup(device);
   *out = s;
   return JACPCG_OK;
 }
@@ -306,6 +309,32 @@ int rzf_precoder(jacpcg_session* s, void* stream, int batch, int M, int K, const
                       gram_prec, refine, (flags & JACPCG_PRECOND_NONE) != 0, (flags & JACPCG_EPILOGUE_FP32) == 0,
                       refine_tol, (float2*)W, ldw, stride_w, (float2*)X_out, (double2*)X64_out, stats);
   });
+}
+
+int rzf_precoder_noalloc(jacpcg_session* s, void* stream, int batch, int M, int K, const jacpcg_c64* H,
+                         int64_t ldh, int64_t stride_h, double xi, double power, double tol, int max_iter,
+                         int precision, int flags, jacpcg_c64* W, int64_t ldw, int64_t stride_w, int32_t* status) {
+  int rc = check_gram_args(batch, M, K, H, ldh, stride_h, xi, nullptr, 0, 0);
+  if (rc) return rc;
+  JP_CHECK(std::isfinite(power) && power > 0.0, "power must be finite and > 0 (got %g)", power);
+  JP_CHECK(std::isfinite(tol) && tol >= 0.0, "tol must be finite and >= 0 (got %g)", tol);
+  JP_CHECK(max_iter >= 0, "max_iter must be >= 0 (got %d)", max_iter);
+  JP_CHECK((flags & ~(JACPCG_PRECOND_NONE | JACPCG_EPILOGUE_FP32)) == 0, "unknown flags 0x%x", flags);
+  JP_CHECK(ldw >= M, "ldw must be >= M (got %lld < %d)", (long long)ldw, M);
+  if (batch > 1) JP_CHECK(stride_w >= ldw * K, "stride_w must be >= ldw * K");
+  if (batch > 0) JP_CHECK(W != nullptr, "W is NULL");
+  if (precision & JACPCG_REFINE_FP64) return fail(JACPCG_E_UNSUPPORTED, "no refinement without allocation");
+  if (precision < 0 || precision > 2) return fail(JACPCG_E_UNSUPPORTED, "unknown precision 0x%x", precision);
+  const size_t need = noalloc_need(batch, K), cap = noalloc_scratch_bytes();
+  JP_CHECK(need <= cap, "batch of %d instances at K = %d needs %zu bytes of scratch, more than its fixed %zu",
+           batch, K, need, cap);
+  rc = check_session(s);
+  if (rc) return rc;
+  if (batch == 0) return JACPCG_OK;
+  JP_HIP(hipSetDevice(s->device));
+  return run_rzf_noalloc(s, (hipStream_t)stream, batch, M, K, (const float2*)H, ldh, stride_h, xi, power, tol,
+                         max_iter, precision, (flags & JACPCG_PRECOND_NONE) != 0,
+                         (flags & JACPCG_EPILOGUE_FP32) == 0, (float2*)W, ldw, stride_w, status);
 }
 
 int rzf_precoder_vr(jacpcg_session* s, void* stream, int batch, int M, int K, const jacpcg_c64* H, int64_t ldh,

@@ -30,6 +30,11 @@ struct Workspace {
 };
 
 int set_error(int code, const char* msg);
+
+// Fixed device workspace of rzf_precoder_noalloc (noalloc.hip).
+hipError_t noalloc_setup(int device);
+size_t noalloc_scratch_bytes();
+size_t noalloc_need(int batch, int K);
 void fill_stats_host(jacpcg_stats* st, int batch, int K, const int32_t* iters, const float* relres,
                      const int32_t* status, const float* beta);
 
@@ -146,3 +151,10 @@ struct jacpcg_session {
                     float2* W, int64_t ldw,
                     int64_t stride_w, float2* X_out, jacpcg_stats* stats);
 };
+
+namespace jacpcg {
+int run_rzf_noalloc(jacpcg_session* s, hipStream_t st, int batch, int M, int K, const float2* H, int64_t ldh,
+                    int64_t stride_h, double xi, double power, double tol, int max_iter, int gram_prec,
+                    bool precond_none, bool split_epilogue, float2* W, int64_t ldw, int64_t stride_w,
+                    int32_t* status);
+}  // namespace jacpcg

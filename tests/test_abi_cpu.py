@@ -213,3 +213,34 @@ def test_header_compiles_as_plain_c_and_structs_match_the_binding(tmp_path):
         assert got[(cname, "size")] == C.sizeof(py), cname
         for fname, _ in py._fields_:
             assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
+
+
+def _noalloc(**kw):
+    a = dict(s=NULL, batch=4, M=64, K=16, H=FAKE, ldh=64, sh=64 * 16, xi=1.0, power=1.0, tol=0.0, it=8, prec=0,
+             flags=0, W=FAKE, ldw=64, sw=64 * 16, status=NULL)
+    a.update(kw)
+    return L.rzf_precoder_noalloc(a["s"], NULL, a["batch"], a["M"], a["K"], a["H"], a["ldh"], a["sh"], a["xi"],
+                                  a["power"], a["tol"], a["it"], a["prec"], a["flags"], a["W"], a["ldw"], a["sw"],
+                                  a["status"])
+
+
+@pytest.mark.parametrize("kw,word", [
+    (dict(K=0), "K"), (dict(M=0), "M"), (dict(xi=-1.0), "xi"), (dict(power=0.0), "power"), (dict(tol=-1.0), "tol"),
+    (dict(it=-1), "max_iter"), (dict(ldw=63), "ldw"), (dict(W=NULL), "W"), (dict(flags=0x4), "flags"),
+])
+def test_noalloc_validation(kw, word):
+    assert _noalloc(**kw) == bd.E_INVALID_ARG
+    assert word in _err()
+
+
+def test_noalloc_rejects_refinement_and_batches_beyond_its_scratch():
+    assert _noalloc(prec=bd.GRAM_FP32 | bd.REFINE_FP64) == bd.E_UNSUPPORTED
+    assert _noalloc(prec=5) == bd.E_UNSUPPORTED
+    # 96 MiB: 1529 instances fit at K = 64, 383 at K = 128, 95 at K = 256; one more does not
+    big = dict(M=1024, ldh=1024, ldw=1024)
+    for K, fit in ((64, 1529), (128, 383), (256, 95)):
+        st = dict(sh=1024 * K, sw=1024 * K, **big)
+        assert _noalloc(batch=fit + 1, K=K, **st) == bd.E_INVALID_ARG
+        assert "scratch" in _err()
+        assert _noalloc(batch=fit, K=K, **st) == bd.E_INVALID_ARG
+        assert "session" in _err()       # fits: only the missing session is left
