@@ -71,6 +71,8 @@ enum {
   JACPCG_GRAM_FP32 = 0,       /* FP32 MFMA, FP32 accumulation */
   JACPCG_GRAM_BF16X3 = 1,     /* split BF16 hi+lo, products hi*hi + hi*lo + lo*hi, FP32 accumulation */
   JACPCG_GRAM_BF16X6 = 2,     /* split BF16 hi+mid+lo (exact split of FP32), six products, FP32 accumulation */
+  JACPCG_GRAM_FP64_ROUNDED = 3, /* with JACPCG_REFINE_FP64 only: the FP64 Gram of the refinement,
+                                   rounded once to FP32 (no separate FP32 Gram launch) */
   JACPCG_REFINE_FP64 = 0x100  /* rzf_precoder only: FP64-residual iterative refinement of X */
 };
 
@@ -126,9 +128,10 @@ int jacpcg_session_set_profiling(jacpcg_session* s, int enable);
  * Synchronises the session's pending events. */
 int jacpcg_session_phase_times(jacpcg_session* s, double* ms_out, int64_t* launches_out, int reset);
 
-/* Replay identical rzf_precoder calls (same arguments and buffers, no stats,
- * no refinement, profiling off) from a captured HIP graph: 1 = on (default),
- * 0 = always launch kernel by kernel. */
+/* Replay identical rzf_precoder calls (same arguments and buffers, the refined
+ * path included; profiling off) from a captured HIP graph: 1 = on (default),
+ * 0 = always launch kernel by kernel. Stats, when asked for, are read after
+ * the replay. */
 int jacpcg_session_set_graphs(jacpcg_session* s, int enable);
 
 /* Autotune the launch choices for one shape: times the Gram and precoder
@@ -184,9 +187,10 @@ int jacpcg_solve(jacpcg_session* s, void* stream, int batch, int K, int nrhs,
 /* Per-call summary, filled on the host after the call synchronises. */
 typedef struct {
   double max_rel_residual;   /* max over instances/columns of ||b - A x|| / ||b|| (recurrence, FP32) */
-  double max_refine_residual;/* refined path: max ||B - A64 X64||_F / ||B||_F at exit, else 0 */
+  double max_refine_residual;/* refined path: max over instances and columns j of the FP64
+                                ||e_j - A64 x_j||_2 at exit, else 0 */
   int32_t max_iters;         /* max PCG iterations over all columns (first solve) */
-  int32_t refine_steps;      /* refined path: correction solves performed */
+  int32_t refine_steps;      /* refined path: most correction solves any column took */
   int32_t worst_status;      /* most severe per-instance status */
   int32_t reserved;
   double beta_pow_min, beta_pow_max;
@@ -196,22 +200,29 @@ typedef struct {
  * by Jacobi-PCG (tol, max_iter as in jacpcg_solve), then W = beta_pow H X with
  * beta_pow = sqrt(power / ||H X||_F^2) per instance (eq. 7 and eq. 15).
  * W: column-major M x K per instance (precoding vector g_k contiguous).
- * precision | JACPCG_REFINE_FP64: after the FP32 solve, X is refined in FP64
- *   (R = I - A64 X64 in FP64 with A64 the FP64 Gram, FP32 PCG on the
- *   correction) until ||R||_F / ||I||_F <= refine_tol or 16 steps. The FP32
- *   solves then use A64 rounded to FP32 as their matrix, so the Gram
- *   precision bits do not apply.
+ * precision | JACPCG_REFINE_FP64: iterative refinement of X in FP64 on the
+ *   device. A64 = H^H H + xi I is formed in FP64 (FP64 matrix cores) for the
+ *   residual only; the FP32 solves use the Gram of the precision bits
+ *   (JACPCG_GRAM_FP32, _BF16X3 or _BF16X6), or A64 rounded once to FP32
+ *   (JACPCG_GRAM_FP64_ROUNDED). After the first solve, each step computes
+ *   R = I - A64 X64 in FP64, and every column j with ||r_j||_2 > refine_tol
+ *   takes a correction: A E_j = r_j / ||r_j|| by FP32 Jacobi-PCG (tol,
+ *   max_iter), X64 += ||r_j|| E_j. A column stops when ||r_j||_2 <= refine_tol;
+ *   at most 16 corrections. The power factor comes from ||H X64||_F^2 in FP64
+ *   and W from X64 rounded to FP32. An instance with a column still above
+ *   refine_tol after 16 corrections reports NOT_CONVERGED.
  * X_out (nullable): column-major K x K c64 copy of X per instance (ld K,
- *   stride K*K). X64_out (nullable): the same in c128 (refined path; the FP32
- *   solution widened otherwise). flags: as jacpcg_solve.
+ *   stride K*K). X64_out (nullable): the same in c128 (the refined X64; the
+ *   FP32 solution widened otherwise). flags: as jacpcg_solve.
  * stats (host, nullable): when given, the call synchronises `stream` and fills
- *   it. The refined path always synchronises (host-driven convergence test).
+ *   it. Without stats no path synchronises (the refined path included).
  * Returns the worst per-instance status when it synchronises, else OK.
  * Non-finite values in an instance's H make its A non-finite: that instance
  *   ends with E_BREAKDOWN within max_iter and its W and X are unspecified; the
  *   other instances are computed exactly as without it (on the refined path
  *   they still stop on their own residuals).
- * Errors: as jacpcg_gram and jacpcg_solve; power <= 0; refine_tol < 0. */
+ * Errors: as jacpcg_gram and jacpcg_solve; power <= 0; refine_tol < 0;
+ *   E_UNSUPPORTED for JACPCG_GRAM_FP64_ROUNDED without JACPCG_REFINE_FP64. */
 int rzf_precoder(jacpcg_session* s, void* stream, int batch, int M, int K,
                  const jacpcg_c64* H, int64_t ldh, int64_t stride_h,
                  double xi, double power, double tol, int max_iter, int precision, int flags,

@@ -39,6 +39,7 @@ E_TIMEOUT = -9
 GRAM_FP32 = 0
 GRAM_BF16X3 = 1
 GRAM_BF16X6 = 2
+GRAM_FP64_ROUNDED = 3
 REFINE_FP64 = 0x100
 PRECOND_JACOBI = 0
 PRECOND_NONE = 1

@@ -294,7 +294,8 @@ int rzf_precoder(jacpcg_session* s, void* stream, int batch, int M, int K, const
   if (batch > 0) JP_CHECK(W != nullptr, "W is NULL");
   const int gram_prec = precision & 0xff;
   const bool refine = (precision & JACPCG_REFINE_FP64) != 0;
-  if (gram_prec > 2 || (precision & ~(0xff | JACPCG_REFINE_FP64)))
+  if (gram_prec > 3 || (gram_prec == JACPCG_GRAM_FP64_ROUNDED && !refine) ||
+      (precision & ~(0xff | JACPCG_REFINE_FP64)))
     return fail(JACPCG_E_UNSUPPORTED, "unknown precision 0x%x", precision);
   rc = check_session(s);
   if (rc) return rc;
@@ -353,7 +354,8 @@ int rzf_precoder_vr(jacpcg_session* s, void* stream, int batch, int M, int K, co
   if (batch > 0) JP_CHECK(W != nullptr, "W is NULL");
   const int gram_prec = precision & 0xff;
   const bool refine = (precision & JACPCG_REFINE_FP64) != 0;
-  if (gram_prec > 2 || (precision & ~(0xff | JACPCG_REFINE_FP64)))
+  if (gram_prec > 3 || (gram_prec == JACPCG_GRAM_FP64_ROUNDED && !refine) ||
+      (precision & ~(0xff | JACPCG_REFINE_FP64)))
     return fail(JACPCG_E_UNSUPPORTED, "unknown precision 0x%x", precision);
   rc = check_session(s);
   if (rc) return rc;
@@ -453,7 +455,8 @@ int rzf_block_precoder(jacpcg_session* s, void* stream, int batch, int M1, int M
   if (batch > 0) JP_CHECK(G != nullptr, "G is NULL");
   const int gram_prec = precision & 0xff;
   const bool refine = (precision & JACPCG_REFINE_FP64) != 0;
-  if (gram_prec > 2 || (precision & ~(0xff | JACPCG_REFINE_FP64)))
+  if (gram_prec > 3 || (gram_prec == JACPCG_GRAM_FP64_ROUNDED && !refine) ||
+      (precision & ~(0xff | JACPCG_REFINE_FP64)))
     return fail(JACPCG_E_UNSUPPORTED, "unknown precision 0x%x", precision);
   rc = check_session(s);
   if (rc) return rc;

@@ -77,6 +77,8 @@ struct PcgLaunch {
   int first;                                // chunked mode: 1 on the first launch
   const int2* tile_span;                    // nullable: user-block antenna spans (as GramLaunch); tiles of A
                                             // whose blocks' spans are disjoint are zero and skipped (K > 64)
+  const double* col_gate;                   // nullable: batch x nrhs; column j is solved only when
+  double gate_tol;                          //   col_gate[j] > gate_tol (or NaN); other columns give x = 0
 };
 
 struct PrecoderLaunch {
@@ -98,6 +100,8 @@ struct PrecoderLaunch {
                                             // blocks whose span misses a workgroup's antennas are skipped
   const int32_t* wg_status;                 // nullable: the solver's per-workgroup statuses (ncb per instance),
   int32_t* status;                          // reduced here into the per-instance status (no separate launch)
+  const double* ref_scale;                  // nullable (refined path): batch x nrhs final ||r_j||; a column
+  double ref_tol;                           //   above ref_tol (or NaN) makes the instance NOT_CONVERGED
 };
 
 struct Gram64Launch {
@@ -107,23 +111,23 @@ struct Gram64Launch {
   double2* A64;                             // batch x K x K row-major, ld K
 };
 
-struct ResidualLaunch {
-  const double2* A64;                       // batch x K x K row-major, ld K
-  const double2* X64;                       // batch x nrhs x K (column-major K x nrhs, ld K)
-  const float2* B; int64_t ldb, ldb_stride; // right-hand sides; NULL => identity
+// One refinement step (B = I): X64 += ||r_j|| E_j for the columns that missed
+// the tolerance at the previous step (step 0: X64 = X32 widened), then
+// R = I - A64 X64 and its column norms.
+struct RefineStepLaunch {
+  const double2* A64;                       // batch x K x K row-major, ld K, exactly Hermitian
+  double2* X64;                             // batch x nrhs x K (column-major K x nrhs, ld K)
+  float2* X32;                              // same layout: the first solve's X (step 0), then X64 rounded
+  const float2* E32;                        // same layout: the previous step's corrections (step > 0)
   int batch, K, nrhs;
+  int step;
   double xi;
-  float2* R32;                              // batch x nrhs x K: r_j / ||r_j|| (next correction RHS)
-  double* scale;                            // batch x nrhs: ||r_j||
+  double tol;                               // column j is converged when ||r_j|| <= tol
+  float2* R32;                              // same layout: r_j / ||r_j|| (next correction RHS)
+  double* scale;                            // batch x nrhs: ||r_j|| (read as the previous step's at entry)
   double* rnorm2;                           // per workgroup: sum_j ||r_j||^2
   double* quad;                             // per workgroup: sum_j Re x_j^H (A64 - xi I) x_j
-};
-
-struct AccumulateLaunch {
-  double2* X64; const float2* E; const double* scale;
-  int batch, K, nrhs;
-  int first;                                // X64 = E instead of X64 += scale * E
-  float2* X32;                              // nullable: rounded copy of the result
+  int32_t* steps;                           // per workgroup: last step that ran (nullable)
 };
 
 // Visibility-region spans: per user the antenna range [first, end) outside
@@ -157,9 +161,8 @@ hipError_t launch_precoder(const PrecoderLaunch& e, hipStream_t s);
 hipError_t launch_gram64(const Gram64Launch& g, hipStream_t s);
 hipError_t launch_narrow_gram(const double2* A64, int K, int batch, double xi, float2* A, int64_t lda,
                               int64_t stride_a, float* gdiag, hipStream_t s);
-hipError_t launch_residual(const ResidualLaunch& r, hipStream_t s);
-hipError_t launch_accumulate(const AccumulateLaunch& a, hipStream_t s);
-int residual_workgroups_per_instance(int nrhs);
+hipError_t launch_refine_step(const RefineStepLaunch& r, hipStream_t s);
+int refine_workgroups_per_instance(int nrhs);
 hipError_t launch_zero_block(float2* G, int64_t ld, int64_t stride, int batch, int row0, int nrows, int col0,
                              int ncols, hipStream_t s);
 hipError_t launch_fill_synthetic(float2* H, size_t n, uint32_t seed, hipStream_t s);

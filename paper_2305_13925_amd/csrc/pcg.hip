@@ -156,6 +156,14 @@ __global__ __launch_bounds__(KT * 64) __attribute__((amdgpu_waves_per_eu(2))) vo
   const bool chunked = p.st.vec != nullptr;
   // A workgroup that already finished in an earlier chunk has nothing to do.
   if (chunked && !p.first && p.st.done[L]) return;
+  // Gated columns (refinement corrections): only columns whose residual
+  // missed the tolerance are solved; a block with none leaves X untouched.
+  // Every wave holds all 32 columns, so the test is workgroup-uniform.
+  bool gate_on = true;
+  if (p.col_gate) {
+    gate_on = jvalid && !(p.col_gate[(int64_t)b * p.nrhs + j] <= p.gate_tol);
+    if (!__any(gate_on)) return;
+  }
 
   const float2* Ab = p.A + (int64_t)b * p.stride_a;
   // A-operand row of this lane and its contiguous half-row.
@@ -269,7 +277,7 @@ __global__ __launch_bounds__(KT * 64) __attribute__((amdgpu_waves_per_eu(2))) vo
     bb = part[0];
     rho = part[1];
     rres = bb;
-    active = jvalid && bb > 0.f;
+    active = jvalid && bb > 0.f && gate_on;
     conv = true;  // reset below for columns that must iterate
     if (active) conv = false;
   } else {

@@ -29,6 +29,10 @@ __device__ __forceinline__ int instance_status(const PrecoderLaunch& e, int b) {
     if (v == kStatusBreakdown) s = kStatusBreakdown;
     else if (v == kStatusNotConverged && s == kStatusOk) s = kStatusNotConverged;
   }
+  if (e.ref_scale && s == kStatusOk) {
+    for (int j = 0; j < e.nrhs; ++j)
+      if (!(e.ref_scale[(int64_t)b * e.nrhs + j] <= e.ref_tol)) s = kStatusNotConverged;
+  }
   return s;
 }
 

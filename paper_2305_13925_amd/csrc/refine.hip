@@ -1,7 +1,7 @@
 // FP64 side of the path: the FP64 Gram A64 = H^H H + xi I (from the same
-// complex64 channel, widened exactly), the refinement residual R = B - A64 X64
-// with its column norms, and the FP64 accumulation X64 += scale * E of the
-// FP32 correction solves. Iterative refinement is not in the paper; it wins
+// complex64 channel, widened exactly) and the refinement step (FP64
+// accumulation X64 += ||r|| E of the FP32 correction solves, the residual
+// R = I - A64 X64 and its column norms). Iterative refinement is not in the paper; it wins
 // back the accuracy the FP32 (or split-BF16) Gram and the FP32 solve lose.
 //
 // v_mfma_f64_16x16x4_f64 layout: A-operand lane l holds A[l%16][l/16],
@@ -169,13 +169,27 @@ __global__ __launch_bounds__(256) void gram64_kernel(Gram64Launch g) {
   }
 }
 
-// R = B - A64 X64 for one instance and 16 columns per workgroup (B = I when
-// `identity`). Wave w owns row tiles w, w+4, ... Per column: ||r_j||^2, the
-// FP32 right-hand side r_j / ||r_j|| of the next correction solve, and
-// Re x_j^H (A64 - xi I) x_j = ||H x_j||^2 (FP64, no cancellation problem).
-constexpr int kResMaxRowTiles = 4;  // K <= 256: 16 row tiles over 4 waves
-
-__global__ __launch_bounds__(256) void residual64_kernel(ResidualLaunch r) {
+// One step of iterative refinement for one instance and 16 right-hand-side
+// columns of B = I (workgroup of 4 waves):
+//   1. X64 of the block's columns: at step 0 the first FP32 solution widened
+//      exactly; at a later step X64 += ||r_j|| E_j for every column j whose
+//      residual at the previous step missed the tolerance (E_j solves
+//      A E_j = r_j / ||r_j|| in FP32). The rounded X64 goes back to X32 for the
+//      precoder. A block whose columns had all converged returns at once:
+//      its X, residual and partial sums stand from the step that ran last.
+//   2. R = I - A64 X64 in FP64 on the matrix cores; per column ||r_j||, the
+//      FP32 right-hand side r_j / ||r_j|| of the next correction solve; per
+//      workgroup sum_j ||r_j||^2 and sum_j Re x_j^H (A64 - xi I) x_j =
+//      sum_j ||H x_j||^2 (FP64, the power factor of the precoder).
+// X64 of the block sits in LDS as the B-operand. A64 is exactly Hermitian,
+// so the A-operand entry A[i][k] is read as conj(A[k][i]): the 16 lanes of one
+// k slot then load 256 contiguous bytes of row k. Wave w owns the row tiles
+// w, w + 4, ...; k is outermost, so its row tiles' products are independent
+// accumulation chains, and the next step's A entries are loaded one step
+// ahead of the products.
+template <int RT>
+__global__ __launch_bounds__(256) void refine_step_kernel(RefineStepLaunch r) {
+  constexpr int KM = 64 * RT;  // largest K of this variant
   const int n16 = (r.nrhs + 15) >> 4;
   const int L = xcd_remap(blockIdx.x, gridDim.x);
   const int b = L / n16, cb = L - b * n16;
@@ -183,40 +197,87 @@ __global__ __launch_bounds__(256) void residual64_kernel(ResidualLaunch r) {
   const int q = lane >> 4, li = lane & 15;
   const int slot_k = q >> 1, comp = q & 1;
   const int K = r.K;
-  const int j = cb * 16 + li;
-  const bool jv = j < r.nrhs;
-  const double2* Ab = r.A64 + (int64_t)b * K * K;
-  const double2* Xb = r.X64 + (int64_t)b * K * r.nrhs;
-  const int ntr = (K + 15) >> 4;
+  const int j0 = cb * 16;
+  const int ncol = min(16, r.nrhs - j0);
+  const int64_t xo = (int64_t)b * K * r.nrhs;
+  double* scale = r.scale + (int64_t)b * r.nrhs;
 
-  // k outermost: the row tiles' products are independent accumulation chains
-  // that share the X operand of each step.
-  doublex4 qr[kResMaxRowTiles], qi[kResMaxRowTiles];
+  if (r.step > 0) {
+    bool need = false;
+    for (int c = 0; c < ncol; ++c) need |= !(scale[j0 + c] <= r.tol);  // NaN keeps refining
+    if (!need) return;
+  }
+
+  __shared__ double2 Xs[16][KM + 1];
+  for (int e = threadIdx.x; e < 16 * K; e += 256) {
+    const int jj = e / K, i = e - jj * K;
+    double2 x = make_double2(0.0, 0.0);
+    if (jj < ncol) {
+      const int64_t o = xo + (int64_t)(j0 + jj) * K + i;
+      if (r.step == 0) {
+        const float2 v = r.X32[o];
+        x = make_double2(v.x, v.y);
+        r.X64[o] = x;
+      } else {
+        x = r.X64[o];
+        const double sc = scale[j0 + jj];
+        if (!(sc <= r.tol)) {
+          const float2 ev = r.E32[o];
+          x.x += sc * (double)ev.x;
+          x.y += sc * (double)ev.y;
+          r.X64[o] = x;
+          r.X32[o] = make_float2((float)x.x, (float)x.y);
+        }
+      }
+    }
+    Xs[jj][i] = x;
+  }
+  if (threadIdx.x == 0 && r.steps) r.steps[L] = r.step;
+  __syncthreads();
+
+  const double2* Ab = r.A64 + (int64_t)b * K * K;
+  const int ntr = (K + 15) >> 4;
+  doublex4 qr[RT], qi[RT];
 #pragma unroll
-  for (int t = 0; t < kResMaxRowTiles; ++t) {
+  for (int t = 0; t < RT; ++t) {
     qr[t] = zero4d();
     qi[t] = zero4d();
   }
-  for (int k0 = 0; k0 < K; k0 += 2) {
+  // A-operand of row tile t at complex step kk: conj(A[kk][rt * 16 + li]).
+  double2 acur[RT], anxt[RT];
+  auto load_a = [&](int k0, double2 (&dst)[RT]) {
     const int kk = k0 + slot_k;
-    const double2 x = (jv && kk < K) ? Xb[(int64_t)j * K + kk] : make_double2(0.0, 0.0);
-    const double xr = comp ? -x.y : x.x, xim = comp ? x.x : x.y;
 #pragma unroll
-    for (int t = 0; t < kResMaxRowTiles; ++t) {
-      const int rt = w + 4 * t;
-      if (rt >= ntr) continue;  // wave-uniform
-      const int ia = rt * 16 + li;  // A-operand row
-      const double2 a = (ia < K && kk < K) ? Ab[(int64_t)ia * K + kk] : make_double2(0.0, 0.0);
-      const double av = comp ? a.y : a.x;
+    for (int t = 0; t < RT; ++t) {
+      const int ia = (w + 4 * t) * 16 + li;
+      dst[t] = (ia < K && kk < K) ? Ab[(int64_t)kk * K + ia] : make_double2(0.0, 0.0);
+    }
+  };
+  load_a(0, acur);
+  for (int k0 = 0; k0 < K; k0 += 2) {
+    if (k0 + 2 < K) load_a(k0 + 2, anxt);
+    const int kk = k0 + slot_k;
+    const double2 x = kk < K ? Xs[li][kk] : make_double2(0.0, 0.0);
+    const double xr = comp ? -x.y : x.x, xim = comp ? x.x : x.y;
+    // Every row tile is formed (rows beyond K read zeros): a branch around
+    // the products, though wave-uniform, makes the compiler move the
+    // accumulators between register files around each one.
+#pragma unroll
+    for (int t = 0; t < RT; ++t) {
+      const double av = comp ? -acur[t].y : acur[t].x;
       qr[t] = mfma64(av, xr, qr[t]);
       qi[t] = mfma64(av, xim, qi[t]);
     }
-  }
-  // Own rows of the result: rt*16 + q + 4*reg, column j.
-  double nr = 0.0, quad = 0.0;
-  double rre[kResMaxRowTiles][4], rim[kResMaxRowTiles][4];
 #pragma unroll
-  for (int t = 0; t < kResMaxRowTiles; ++t) {
+    for (int t = 0; t < RT; ++t) acur[t] = anxt[t];
+  }
+
+  // Own rows of the result: rt*16 + q + 4*g, column j0 + li.
+  const bool jv = li < ncol;
+  double nr = 0.0, quad = 0.0;
+  double rre[RT][4], rim[RT][4];
+#pragma unroll
+  for (int t = 0; t < RT; ++t) {
     const int rt = w + 4 * t;
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
@@ -224,17 +285,10 @@ __global__ __launch_bounds__(256) void residual64_kernel(ResidualLaunch r) {
       rre[t][g] = 0.0;
       rim[t][g] = 0.0;
       if (rt >= ntr || i >= K || !jv) continue;
-      double2 bv = make_double2(0.0, 0.0);
-      if (r.B) {
-        const float2 bf = r.B[(int64_t)b * r.ldb_stride + (int64_t)j * r.ldb + i];  // caller's B
-        bv = make_double2(bf.x, bf.y);
-      } else if (i == j) {
-        bv.x = 1.0;
-      }
-      rre[t][g] = bv.x - qr[t][g];
-      rim[t][g] = bv.y - qi[t][g];
+      rre[t][g] = (i == j0 + li ? 1.0 : 0.0) - qr[t][g];
+      rim[t][g] = -qi[t][g];
       nr += rre[t][g] * rre[t][g] + rim[t][g] * rim[t][g];
-      const double2 x = Xb[(int64_t)j * K + i];
+      const double2 x = Xs[li][i];
       quad += x.x * qr[t][g] + x.y * qi[t][g] - r.xi * (x.x * x.x + x.y * x.y);
     }
   }
@@ -253,24 +307,23 @@ __global__ __launch_bounds__(256) void residual64_kernel(ResidualLaunch r) {
   const double sc = sqrt(nr);
   const double inv = sc > 0.0 ? 1.0 / sc : 0.0;
 #pragma unroll
-  for (int t = 0; t < kResMaxRowTiles; ++t) {
+  for (int t = 0; t < RT; ++t) {
     const int rt = w + 4 * t;
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
       const int i = rt * 16 + q + 4 * g;
       if (rt < ntr && i < K && jv)
-        r.R32[(int64_t)b * K * r.nrhs + (int64_t)j * K + i] =
-            make_float2((float)(rre[t][g] * inv), (float)(rim[t][g] * inv));
+        r.R32[xo + (int64_t)(j0 + li) * K + i] = make_float2((float)(rre[t][g] * inv), (float)(rim[t][g] * inv));
     }
   }
-  if (w == 0 && q == 0 && jv) r.scale[(int64_t)b * r.nrhs + j] = sc;
+  if (w == 0 && q == 0 && jv) scale[j0 + li] = sc;
   if (threadIdx.x == 0) {
-    double s = 0.0, s2 = 0.0;
+    double s1 = 0.0, s2 = 0.0;
     for (int c = 0; c < 16; ++c) {
-      s += cs[0][0][c] + cs[0][1][c] + cs[0][2][c] + cs[0][3][c];
+      s1 += cs[0][0][c] + cs[0][1][c] + cs[0][2][c] + cs[0][3][c];
       s2 += cs[1][0][c] + cs[1][1][c] + cs[1][2][c] + cs[1][3][c];
     }
-    r.rnorm2[L] = s;
+    r.rnorm2[L] = s1;
     r.quad[L] = s2;
   }
 }
@@ -287,26 +340,6 @@ __global__ void narrow_gram_kernel(const double2* __restrict__ A64, int K, doubl
   const double2 v = A64[(int64_t)b * K * K + idx];
   A[(int64_t)b * stride_a + (int64_t)i * lda + j] = make_float2((float)v.x, (float)v.y);
   if (i == j && gdiag) gdiag[(int64_t)b * K + i] = (float)(v.x - xi);
-}
-
-__global__ void accumulate_kernel(AccumulateLaunch a) {
-  const int b = blockIdx.y;
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= a.K * a.nrhs) return;
-  const int j = idx / a.K;
-  const int64_t o = (int64_t)b * a.K * a.nrhs + idx;
-  const float2 e = a.E[o];
-  double2 x;
-  if (a.first) {
-    x = make_double2(e.x, e.y);
-  } else {
-    const double s = a.scale[(int64_t)b * a.nrhs + j];
-    x = a.X64[o];
-    x.x += s * (double)e.x;
-    x.y += s * (double)e.y;
-  }
-  a.X64[o] = x;
-  if (a.X32) a.X32[o] = make_float2((float)x.x, (float)x.y);
 }
 
 __global__ void widen_kernel(const float2* __restrict__ X, int64_t ldx, int64_t stride_x, int K, int n,
@@ -377,20 +410,21 @@ hipError_t launch_narrow_gram(const double2* A64, int K, int batch, double xi, f
   return hipGetLastError();
 }
 
-hipError_t launch_residual(const ResidualLaunch& r, hipStream_t s) {
+hipError_t launch_refine_step(const RefineStepLaunch& r, hipStream_t s) {
   if (r.batch == 0) return hipSuccess;
-  if (r.K > 16 * 4 * kResMaxRowTiles) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(residual64_kernel, dim3(r.batch * ((r.nrhs + 15) / 16)), dim3(256), 0, s, r);
+  const dim3 grid((unsigned)(r.batch * refine_workgroups_per_instance(r.nrhs)));
+  if (r.K <= 64)
+    hipLaunchKernelGGL(refine_step_kernel<1>, grid, dim3(256), 0, s, r);
+  else if (r.K <= 128)
+    hipLaunchKernelGGL(refine_step_kernel<2>, grid, dim3(256), 0, s, r);
+  else if (r.K <= 256)
+    hipLaunchKernelGGL(refine_step_kernel<4>, grid, dim3(256), 0, s, r);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
-int residual_workgroups_per_instance(int nrhs) { return (nrhs + 15) / 16; }
-
-hipError_t launch_accumulate(const AccumulateLaunch& a, hipStream_t s) {
-  if (a.batch == 0) return hipSuccess;
-  hipLaunchKernelGGL(accumulate_kernel, dim3((a.K * a.nrhs + 255) / 256, a.batch), dim3(256), 0, s, a);
-  return hipGetLastError();
-}
+int refine_workgroups_per_instance(int nrhs) { return (nrhs + 15) / 16; }
 
 hipError_t launch_widen(const float2* X, int64_t ldx, int64_t stride_x, int batch, int K, int n, double2* out,
                         hipStream_t s) {

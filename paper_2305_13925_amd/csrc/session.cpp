@@ -3,7 +3,9 @@
 #include "session.hpp"
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
+#include <limits>
 
 using namespace jacpcg;
 
@@ -170,7 +172,8 @@ int jacpcg_session::run_rzf(hipStream_t st, int batch, int M, int K, const float
                             bool split_epilogue, double refine_tol, float2* W, int64_t ldw, int64_t stride_w,
                             float2* X_out, double2* X64_out, jacpcg_stats* stats, bool vr_sparse,
                             const int32_t* user_span) {
-  // nrhs right-hand-side columns (B = NULL: the identity, nrhs = K).
+  // nrhs right-hand-side columns (B = NULL: the identity, nrhs = K; the
+  // refined path always has B = I).
   const int ncb = (nrhs + 31) / 32;
   const size_t KK = (size_t)K * K;
   const size_t KN = (size_t)K * nrhs;
@@ -185,14 +188,15 @@ int jacpcg_session::run_rzf(hipStream_t st, int batch, int M, int K, const float
   const size_t oR = ws.take<float>((size_t)batch * nrhs);
   const size_t oB = ws.take<float>(batch);
   // refinement buffers
-  const int n16 = residual_workgroups_per_instance(K);
+  const int n16 = refine_workgroups_per_instance(K);
   const size_t oA64 = refine ? ws.take<double2>(batch * KK) : 0;
-  const size_t oX64 = refine ? ws.take<double2>(batch * KK) : 0;
+  const size_t oX64 = (refine && !X64_out) ? ws.take<double2>(batch * KK) : 0;
   const size_t oR32 = refine ? ws.take<float2>(batch * KK) : 0;
   const size_t oE32 = refine ? ws.take<float2>(batch * KK) : 0;
   const size_t oSc = refine ? ws.take<double>(batch * (size_t)K) : 0;
   const size_t oRn = refine ? ws.take<double>((size_t)batch * n16) : 0;
   const size_t oQd = refine ? ws.take<double>((size_t)batch * n16) : 0;
+  const size_t oSt = refine ? ws.take<int32_t>((size_t)batch * n16) : 0;
   const size_t oWG2 = refine ? ws.take<int32_t>((size_t)batch * ncb) : 0;
   // visibility-region spans per 32-user block (sparse Gram tiles and solver)
   const int nt = (K + 31) / 32;
@@ -209,12 +213,22 @@ int jacpcg_session::run_rzf(hipStream_t st, int batch, int M, int K, const float
   int32_t* iters = at<int32_t>(oI);
   float* relres = at<float>(oR);
   float* beta = at<float>(oB);
+  double2* A64 = refine ? at<double2>(oA64) : nullptr;
+  double2* X64 = refine ? (X64_out ? X64_out : at<double2>(oX64)) : nullptr;
+  double* scale = refine ? at<double>(oSc) : nullptr;
+  double* quad = refine ? at<double>(oQd) : nullptr;
+  int32_t* rsteps = refine ? at<int32_t>(oSt) : nullptr;
 
-  // Gram -> persistent PCG -> status; on stream q, phases timed when `timed_run`.
-  auto enqueue_solve = [&](hipStream_t q, bool timed_run) -> hipError_t {
+  // The whole path on stream q, phases timed when `timed_run`:
+  //   Gram (and the FP64 Gram) -> persistent PCG -> [refinement steps] -> precoder.
+  // The refinement runs on the device: kMaxRefineSteps correction solves are
+  // enqueued, and each column stops taking corrections once its FP64 residual
+  // meets refine_tol (later launches find nothing left to do for it).
+  auto enqueue_all = [&](hipStream_t q, bool timed_run) -> hipError_t {
     auto run = [&](int phase, auto&& launch) -> hipError_t {
       return timed_run ? timed(q, phase, launch) : launch();
     };
+    hipError_t e = hipSuccess;
     if (use_spans) {
       SpanLaunch sl{};
       sl.H = H;
@@ -225,17 +239,17 @@ int jacpcg_session::run_rzf(hipStream_t st, int batch, int M, int K, const float
       sl.M = M;
       sl.K = K;
       sl.tile_span = const_cast<int2*>(tspan);
-      hipError_t es = launch_spans(sl, q);
-      if (es != hipSuccess) return es;
+      e = launch_spans(sl, q);
+      if (e != hipSuccess) return e;
     }
-    hipError_t e = hipSuccess;
     if (refine) {
-      // The refinement needs the FP64 Gram anyway: the FP32 solves take it
-      // rounded once to FP32 (the Gram precision bits do not apply).
-      Gram64Launch g64{H, ldh, stride_h, batch, M, K, xi, at<double2>(oA64)};
+      Gram64Launch g64{H, ldh, stride_h, batch, M, K, xi, A64};
       e = run(JACPCG_PHASE_GRAM64, [&] { return launch_gram64(g64, q); });
       if (e != hipSuccess) return e;
-      e = launch_narrow_gram(at<double2>(oA64), K, batch, xi, A, K, (int64_t)KK, gdiag, q);
+    }
+    if (refine && gram_prec == JACPCG_GRAM_FP64_ROUNDED) {
+      // the FP32 solves take the FP64 Gram rounded once to FP32
+      e = launch_narrow_gram(A64, K, batch, xi, A, K, (int64_t)KK, gdiag, q);
       if (e != hipSuccess) return e;
     } else {
       GramLaunch g{};
@@ -277,15 +291,58 @@ int jacpcg_session::run_rzf(hipStream_t st, int batch, int M, int K, const float
     p.iters = iters;
     p.relres = relres;
     p.wg_status = wgs;
-    p.gdiag = gdiag;
+    p.gdiag = refine ? nullptr : gdiag;  // refined path: the power factor comes from FP64 X
     p.fpart = fpart;
     p.tile_span = tspan;
     e = run(JACPCG_PHASE_SOLVE, [&] { return launch_pcg(p, q, nullptr); });
     if (e != hipSuccess) return e;
-    return hipSuccess;  // the per-instance status is reduced by the precoder kernel
-  };
-  // W = beta_pow H X (and the FP64 copy of X) on stream q.
-  auto enqueue_precoder = [&](hipStream_t q, bool timed_run, const double* quad64, int nq) -> hipError_t {
+
+    if (refine) {
+      RefineStepLaunch rs{};
+      rs.A64 = A64;
+      rs.X64 = X64;
+      rs.X32 = X;
+      rs.E32 = at<float2>(oE32);
+      rs.batch = batch;
+      rs.K = K;
+      rs.nrhs = K;
+      rs.xi = xi;
+      rs.tol = refine_tol;
+      rs.R32 = at<float2>(oR32);
+      rs.scale = scale;
+      rs.rnorm2 = at<double>(oRn);
+      rs.quad = quad;
+      rs.steps = rsteps;
+      PcgLaunch pc{};
+      pc.A = A;
+      pc.lda = K;
+      pc.stride_a = (int64_t)KK;
+      pc.B = rs.R32;
+      pc.ldb = K;
+      pc.stride_b = (int64_t)KK;
+      pc.X = at<float2>(oE32);
+      pc.ldx = K;
+      pc.stride_x = (int64_t)KK;
+      pc.batch = batch;
+      pc.K = K;
+      pc.nrhs = K;
+      pc.tol = (float)tol;
+      pc.max_iter = max_iter;
+      pc.precond_none = precond_none;
+      pc.wg_status = at<int32_t>(oWG2);
+      pc.tile_span = tspan;
+      pc.col_gate = scale;
+      pc.gate_tol = refine_tol;
+      for (int step = 0;; ++step) {
+        rs.step = step;
+        e = run(JACPCG_PHASE_RESIDUAL, [&] { return launch_refine_step(rs, q); });
+        if (e != hipSuccess) return e;
+        if (step == kMaxRefineSteps) break;
+        e = run(JACPCG_PHASE_SOLVE, [&] { return launch_pcg(pc, q, nullptr); });
+        if (e != hipSuccess) return e;
+      }
+    }
+
     PrecoderLaunch E{};
     E.H = H;
     E.ldh = ldh;
@@ -308,11 +365,12 @@ int jacpcg_session::run_rzf(hipStream_t st, int batch, int M, int K, const float
     E.status = status;
     E.split = split_epilogue ? 3 : 0;
     E.nj = tuner.precoder_nj(M, K, E.split);
-    E.fpart64 = quad64;  // refined path: ||H X64||^2 from the last FP64 residual
-    E.ncb64 = nq;
+    E.fpart64 = refine ? quad : nullptr;  // ||H X64||^2 from the last FP64 residual
+    E.ncb64 = n16;
+    E.ref_scale = scale;
+    E.ref_tol = refine_tol;
     E.tile_span = tspan;
-    hipError_t e = timed_run ? timed(q, JACPCG_PHASE_EPILOGUE, [&] { return launch_precoder(E, q); })
-                             : launch_precoder(E, q);
+    e = run(JACPCG_PHASE_EPILOGUE, [&] { return launch_precoder(E, q); });
     if (e != hipSuccess) return e;
     if (X64_out && !refine) e = launch_widen(X, K, (int64_t)KN, batch, K, nrhs, X64_out, q);
     return e;
@@ -320,21 +378,22 @@ int jacpcg_session::run_rzf(hipStream_t st, int batch, int M, int K, const float
 
   // Repeated calls with identical arguments replay one captured HIP graph
   // (captured on a side stream, launched on the caller's stream).
-  if (!refine && !stats && use_graphs && !profiling) {
+  bool launched = false;
+  if (use_graphs && !profiling) {
     const uint64_t key = graph_key({(uint64_t)batch, (uint64_t)M, (uint64_t)K, (uint64_t)nrhs,
                                     (uint64_t)(uintptr_t)B, (uint64_t)ldb, (uint64_t)stride_b, (uint64_t)(uintptr_t)H,
                                     (uint64_t)ldh, (uint64_t)stride_h, bits_of(xi), bits_of(power), bits_of(tol),
                                     (uint64_t)max_iter, (uint64_t)gram_prec, (uint64_t)precond_none,
                                     (uint64_t)split_epilogue, (uint64_t)(uintptr_t)W, (uint64_t)ldw,
                                     (uint64_t)stride_w, (uint64_t)(uintptr_t)X_out, (uint64_t)(uintptr_t)X64_out,
-                                    (uint64_t)(uintptr_t)arena, (uint64_t)vr_sparse, (uint64_t)(uintptr_t)user_span});
+                                    (uint64_t)(uintptr_t)arena, (uint64_t)vr_sparse, (uint64_t)(uintptr_t)user_span,
+                                    (uint64_t)refine, bits_of(refine ? refine_tol : 0.0)});
     hipGraphExec_t ex = graph_lookup(key);
     if (!ex) {
       hipStream_t cs = capture_stream();
       hipError_t e = cs ? hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed) : hipErrorInvalidValue;
       if (e == hipSuccess) {
-        hipError_t e1 = enqueue_solve(cs, false);
-        if (e1 == hipSuccess) e1 = enqueue_precoder(cs, false, nullptr, 0);
+        const hipError_t e1 = enqueue_all(cs, false);
         hipGraph_t graph = nullptr;
         e = hipStreamEndCapture(cs, &graph);
         if (e1 == hipErrorNotSupported) {
@@ -352,103 +411,46 @@ int jacpcg_session::run_rzf(hipStream_t st, int batch, int M, int K, const float
     if (ex) {
       hipError_t e = hipGraphLaunch(ex, st);
       if (e != hipSuccess) return hip_error(this, e, "graph launch");
-      return JACPCG_OK;
+      launched = true;
     }
     // capture not possible: fall through to the eager launches
   }
-
-  {
-    hipError_t e = enqueue_solve(st, true);
+  if (!launched) {
+    hipError_t e = enqueue_all(st, true);
     if (e == hipErrorNotSupported) return set_error(JACPCG_E_UNSUPPORTED, "Gram precision not available");
-    if (e != hipSuccess) return hip_error(this, e, "gram/pcg launch");
+    if (e != hipSuccess) return hip_error(this, e, "precoder path launch");
   }
 
-  // ---- FP64-residual iterative refinement (B = I) --------------------------
-  int refine_steps = 0;
-  double refine_res = 0.0;
-  double2* X64 = refine ? at<double2>(oX64) : nullptr;
-  double* quad = refine ? at<double>(oQd) : nullptr;
-  if (refine) {
-    double2* A64 = at<double2>(oA64);
-    float2* R32 = at<float2>(oR32);
-    float2* E32 = at<float2>(oE32);
-    double* scale = at<double>(oSc);
-    double* rn2 = at<double>(oRn);
-    // A64 was formed before the first solve.
-    AccumulateLaunch acc{X64, X, nullptr, batch, K, K, 1, nullptr};
-    hipError_t e = launch_accumulate(acc, st);  // X64 = X (exact widening)
-    if (e != hipSuccess) return hip_error(this, e, "accumulate launch");
-    double* h_rn = (double*)host_scratch((size_t)batch * n16 * sizeof(double));
-    if (!h_rn) return set_error(JACPCG_E_OUT_OF_MEMORY, "pinned host staging allocation failed");
-    for (int step = 0;; ++step) {
-      ResidualLaunch rl{A64, X64, nullptr, 0, 0, batch, K, K, xi, R32, scale, rn2, quad};
-      e = timed(st, JACPCG_PHASE_RESIDUAL, [&] { return launch_residual(rl, st); });
-      if (e != hipSuccess) return hip_error(this, e, "residual launch");
-      S_HIP(hipMemcpyAsync(h_rn, rn2, (size_t)batch * n16 * sizeof(double), hipMemcpyDeviceToHost, st));
-      S_HIP(hipStreamSynchronize(st));
-      refine_res = 0.0;
-      for (int b = 0; b < batch; ++b) {
-        double f = 0.0;
-        for (int c = 0; c < n16; ++c) f += h_rn[(size_t)b * n16 + c];
-        refine_res = std::max(refine_res, std::sqrt(f / K));  // ||R||_F / ||I||_F
-      }
-      if (refine_res <= refine_tol || step >= kMaxRefineSteps) break;
-      // correction: A E = R / ||r_j|| column by column, in FP32
-      PcgLaunch pc{};
-      pc.A = A;
-      pc.lda = K;
-      pc.stride_a = (int64_t)KK;
-      pc.B = R32;
-      pc.ldb = K;
-      pc.stride_b = (int64_t)KK;
-      pc.X = E32;
-      pc.ldx = K;
-      pc.stride_x = (int64_t)KK;
-      pc.batch = batch;
-      pc.K = K;
-      pc.nrhs = K;
-      pc.tol = (float)tol;
-      pc.max_iter = max_iter;
-      pc.precond_none = precond_none;
-      pc.wg_status = at<int32_t>(oWG2);
-      pc.tile_span = tspan;
-      e = timed(st, JACPCG_PHASE_SOLVE, [&] { return launch_pcg(pc, st, nullptr); });
-      if (e != hipSuccess) return hip_error(this, e, "correction pcg launch");
-      AccumulateLaunch ac{X64, E32, scale, batch, K, K, 0, X};
-      e = launch_accumulate(ac, st);
-      if (e != hipSuccess) return hip_error(this, e, "accumulate launch");
-      ++refine_steps;
-    }
-  }
-
-  {
-    hipError_t e = enqueue_precoder(st, true, quad, n16);
-    if (e != hipSuccess) return hip_error(this, e, "precoder launch");
-    if (X64_out && refine) {
-      e = hipMemcpyAsync(X64_out, X64, batch * KK * sizeof(double2), hipMemcpyDeviceToDevice, st);
-      if (e != hipSuccess) return hip_error(this, e, "X64 output");
-    }
-  }
-
-  jacpcg_stats local_stats;
-  if (!stats && refine) stats = &local_stats;  // the refined path synchronises anyway
   if (!stats) return JACPCG_OK;
-  const size_t hb = (size_t)batch * nrhs * 8 + (size_t)batch * 8;
+  const size_t hb = (size_t)batch * nrhs * 8 + (size_t)batch * 8 +
+                    (refine ? (size_t)batch * K * sizeof(double) + (size_t)batch * n16 * 4 : 0);
   char* h = (char*)host_scratch(hb);
   if (!h) return set_error(JACPCG_E_OUT_OF_MEMORY, "pinned host staging allocation failed");
   int32_t* h_it = (int32_t*)h;
   float* h_rr = (float*)(h_it + (size_t)batch * nrhs);
   int32_t* h_st = (int32_t*)(h_rr + (size_t)batch * nrhs);
   float* h_b = (float*)(h_st + batch);
+  double* h_sc = (double*)(h_b + batch);  // 8-byte aligned: 8 (batch * nrhs + batch) bytes precede it
+  int32_t* h_steps = (int32_t*)(h_sc + (refine ? (size_t)batch * K : 0));
   S_HIP(hipMemcpyAsync(h_it, iters, (size_t)batch * nrhs * 4, hipMemcpyDeviceToHost, st));
   S_HIP(hipMemcpyAsync(h_rr, relres, (size_t)batch * nrhs * 4, hipMemcpyDeviceToHost, st));
   S_HIP(hipMemcpyAsync(h_st, status, (size_t)batch * 4, hipMemcpyDeviceToHost, st));
   S_HIP(hipMemcpyAsync(h_b, beta, (size_t)batch * 4, hipMemcpyDeviceToHost, st));
+  if (refine) {
+    S_HIP(hipMemcpyAsync(h_sc, scale, (size_t)batch * K * sizeof(double), hipMemcpyDeviceToHost, st));
+    S_HIP(hipMemcpyAsync(h_steps, rsteps, (size_t)batch * n16 * 4, hipMemcpyDeviceToHost, st));
+  }
   S_HIP(hipStreamSynchronize(st));
   fill_stats_host(stats, batch, nrhs, h_it, h_rr, h_st, h_b);
-  stats->refine_steps = refine_steps;
-  stats->max_refine_residual = refine_res;
-  if (refine && refine_res > refine_tol && stats->worst_status == JACPCG_OK) stats->worst_status = JACPCG_NOT_CONVERGED;
+  if (refine) {
+    double worst = 0.0;
+    for (size_t i = 0; i < (size_t)batch * K; ++i)
+      worst = std::isfinite(h_sc[i]) ? std::max(worst, h_sc[i]) : std::numeric_limits<double>::infinity();
+    int steps_max = 0;
+    for (size_t i = 0; i < (size_t)batch * n16; ++i) steps_max = std::max(steps_max, (int)h_steps[i]);
+    stats->refine_steps = steps_max;
+    stats->max_refine_residual = worst;
+  }
   return stats->worst_status;
 }
 

@@ -244,3 +244,13 @@ def test_noalloc_rejects_refinement_and_batches_beyond_its_scratch():
         assert "scratch" in _err()
         assert _noalloc(batch=fit, K=K, **st) == bd.E_INVALID_ARG
         assert "session" in _err()       # fits: only the missing session is left
+
+
+def test_fp64_rounded_gram_needs_refinement():
+    common = (NULL, NULL, 2, 64, 16, FAKE, 64, 64 * 16, 1.0, 1.0, 0.0, 8)
+    rc = L.rzf_precoder(*common, bd.GRAM_FP64_ROUNDED, 0, 1e-10, FAKE, 64, 64 * 16, NULL, NULL, NULL)
+    assert rc == bd.E_UNSUPPORTED
+    # with refinement the precision is accepted: only the missing session is left
+    rc = L.rzf_precoder(*common, bd.GRAM_FP64_ROUNDED | bd.REFINE_FP64, 0, 1e-10, FAKE, 64, 64 * 16, NULL, NULL,
+                        NULL)
+    assert rc == bd.E_INVALID_ARG and "session" in _err()

@@ -66,6 +66,34 @@ def test_graph_replay_equals_eager(torch, M, K, batch, precision, flags):
                 assert err <= 1e-5
 
 
+@pytest.mark.parametrize("precision", [bd.GRAM_BF16X3, bd.GRAM_FP64_ROUNDED])
+def test_refined_graph_replay_equals_eager(torch, precision):
+    # The refined path runs its convergence test on the device, so it replays
+    # from a graph too: every replay equals the eager launches bit for bit.
+    rng = np.random.default_rng(11)
+    batch, K, M, xi = 3, 128, 1024, 12.8
+    inputs = [chan(rng, batch, K, M) for _ in range(3)]
+    prec = precision | bd.REFINE_FP64
+    with bd.Session(0) as eager, bd.Session(0) as graphed:
+        eager.set_graphs(False)
+        H = torch.empty((batch, K, M), dtype=torch.complex64, device="cuda")
+        W = torch.empty_like(H)
+        X64 = torch.empty((batch, K, K), dtype=torch.complex128, device="cuda")
+        for rep in range(5):
+            H.copy_(torch.from_numpy(inputs[rep % len(inputs)]))
+            bd.rzf_precoder(graphed, H, xi, tol=1e-6, max_iter=64, precision=prec, W=W, X64_out=X64)
+            W_g, X_g = W.clone(), X64.clone()
+            _ = (H.abs() ** 2).sum()
+            torch.cuda.synchronize()
+            X_e = torch.empty_like(X64)
+            W_e, st, rc = bd.rzf_precoder(eager, H, xi, tol=1e-6, max_iter=64, precision=prec, X64_out=X_e,
+                                          stats=True)
+            torch.cuda.synchronize()
+            assert rc == bd.OK and st["max_refine_residual"] <= 1e-10, st
+            assert torch.equal(W_g, W_e), f"replay {rep}: W differs from the eager launches"
+            assert torch.equal(X_g, X_e), f"replay {rep}: X64 differs from the eager launches"
+
+
 def test_graph_cache_follows_workspace_growth(torch):
     # A larger call grows (moves) the workspace; a later replay of the small
     # shape must not use the freed workspace.

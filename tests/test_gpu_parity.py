@@ -313,7 +313,10 @@ def test_full_size_sampled(torch, sess, name, T, samples):
 REFINE_TOL = 1e-10
 
 
-@pytest.mark.parametrize("prec", [bd.GRAM_FP32, bd.GRAM_BF16X3, bd.GRAM_BF16X6])
+REFINED_PRECISIONS = [bd.GRAM_FP32, bd.GRAM_BF16X3, bd.GRAM_BF16X6, bd.GRAM_FP64_ROUNDED]
+
+
+@pytest.mark.parametrize("prec", REFINED_PRECISIONS)
 @pytest.mark.parametrize("name,gain,n,tol,T", [("precision", "normalised", 2, 1e-6, 64),
                                                ("precision", "literal", 2, 0.0, 16),
                                                ("batched", "normalised", 3, 1e-5, 32)])
@@ -369,7 +372,7 @@ def test_refined_full_size_precision_sampled(torch, sess):
         assert rel(Xn[b].T, Xs) <= REFINE_TOL
 
 
-@pytest.mark.parametrize("prec", [bd.GRAM_FP32, bd.GRAM_BF16X6])
+@pytest.mark.parametrize("prec", REFINED_PRECISIONS)
 @pytest.mark.parametrize("M,K", [(333, 100), (344, 100), (333, 200), (37, 40)])
 def test_refined_ragged_shapes(torch, sess, prec, M, K):
     # The FP64 Gram works in 64 x 64 blocks of A and stages 16 antennas at a
@@ -392,3 +395,52 @@ def test_refined_ragged_shapes(torch, sess, prec, M, K):
         print(f"refined ragged M={M} K={K} prec={prec} b={b}: steps {st['refine_steps']} X64 err {ex:.2e} W err {ew:.2e}")
         assert ex <= REFINE_TOL
         assert ew <= 1e-6
+
+
+def test_refined_solves_use_the_requested_gram(torch, sess):
+    # With a refinement tolerance no column misses, the refined call's X is the
+    # first FP32 solve's: it must equal the unrefined call's X for the same
+    # Gram precision bit for bit, and differ between precisions (the FP32
+    # solves run on the Gram the precision bits name; A64 feeds only the
+    # FP64 residual).
+    w = workload("precision", gain="normalised")
+    H = dev(torch, channel_batch(w, n=2))
+    xi = w.xi_values()[-1]
+    Xs = {}
+    for prec in REFINED_PRECISIONS:
+        X_ref = torch.empty((2, w.K, w.K), dtype=torch.complex64, device="cuda")
+        _, st, rc = bd.rzf_precoder(sess, H, xi, tol=1e-6, max_iter=64, precision=prec | bd.REFINE_FP64,
+                                    refine_tol=1e30, X_out=X_ref, stats=True)
+        assert rc == bd.OK and st["refine_steps"] == 0, st
+        if prec != bd.GRAM_FP64_ROUNDED:
+            X_plain = torch.empty_like(X_ref)
+            bd.rzf_precoder(sess, H, xi, tol=1e-6, max_iter=64, precision=prec, X_out=X_plain)
+            torch.cuda.synchronize()
+            assert torch.equal(X_ref, X_plain), prec
+        Xs[prec] = X_ref
+    for i, a in enumerate(REFINED_PRECISIONS):
+        for b in REFINED_PRECISIONS[i + 1:]:
+            assert not torch.equal(Xs[a], Xs[b]), (a, b)
+    # the two-part split Gram is the least accurate: it needs the most corrections
+    steps = {}
+    for prec in REFINED_PRECISIONS:
+        _, st, rc = bd.rzf_precoder(sess, H, xi, tol=1e-6, max_iter=64, precision=prec | bd.REFINE_FP64,
+                                    refine_tol=REFINE_TOL, stats=True)
+        assert rc == bd.OK and st["max_refine_residual"] <= REFINE_TOL
+        steps[prec] = st["refine_steps"]
+    print("refinement steps by Gram precision:", steps)
+    assert steps[bd.GRAM_BF16X3] >= max(steps[bd.GRAM_FP32], steps[bd.GRAM_FP64_ROUNDED]) >= 1
+
+
+def test_refined_not_converged_status(torch, sess):
+    # A tolerance below what FP64 can reach leaves columns above it after the
+    # 16 corrections: NOT_CONVERGED, with X64 still at the FP64 solution.
+    w = workload("precision", gain="normalised")
+    Hn = channel_batch(w, n=1)
+    xi = w.xi_values()[-1]
+    X64 = torch.empty((1, w.K, w.K), dtype=torch.complex128, device="cuda")
+    _, st, rc = bd.rzf_precoder(sess, dev(torch, Hn), xi, tol=1e-6, max_iter=64,
+                                precision=bd.GRAM_FP32 | bd.REFINE_FP64, refine_tol=1e-30, X64_out=X64, stats=True)
+    assert rc == bd.NOT_CONVERGED and st["refine_steps"] == 16, st
+    Xs, _, _ = oracle.direct_rzf(Hn[0].T.astype(np.complex128), xi)
+    assert rel(X64[0].cpu().numpy().T, Xs) <= REFINE_TOL
