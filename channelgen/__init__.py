@@ -16,6 +16,7 @@ from .xlmimo import (  # noqa: F401
     request_channels,
     instance_matrix,
     device_pool,
+    device_pool_r,
     block_channel_instance,
     block_channel_batch,
     vr_order,

@@ -272,3 +272,47 @@ def device_pool(M, S, K, r, vr, n, seed, device="cuda", gain="literal"):
     beta = d ** -3.7 if gain == "literal" else (d / 10.0) ** -3.7
     h = (beta.sqrt()[..., None, None] * y).reshape(n, K, M)
     return h.to(torch.complex64).contiguous()
+
+
+def device_pool_r(M, S, K, r_range, vr, n, seed, device="cuda", gain="literal", chunk=16):
+    """Like ``device_pool``, but every instance draws its own correlation
+    coefficient r ~ U[r_range] (the serving workload's per-request r), so the
+    AR(1) factor differs per instance. Drawn in chunks of ``chunk`` instances
+    to bound the temporary memory. Returns (complex64 [n, K, M], r per instance)."""
+    import torch
+    if M % S:
+        raise ValueError("M must be a multiple of S")
+    Ms = M // S
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    lo_r, hi_r = float(r_range[0]), float(r_range[1])
+    rs = torch.rand((n,), generator=g, device=device, dtype=torch.float64) * (hi_r - lo_r) + lo_r
+    out = torch.empty((n, K, M), dtype=torch.complex64, device=device)
+    i = torch.arange(Ms, device=device)
+    expo = (i[:, None] - i[None, :]).to(torch.float64)
+    lo, hi = int(vr[0]), min(int(vr[1]), S)
+    lo = max(1, min(lo, hi))
+    sub = torch.arange(S, device=device)
+    for c0 in range(0, n, chunk):
+        m = min(chunk, n - c0)
+        r = rs[c0:c0 + m]
+        # lower-triangular AR(1) factors, one per instance: L[i, j] = r^(i-j) (i >= j),
+        # columns after the first scaled by sqrt(1 - r^2)
+        L = torch.where(expo[None] >= 0, r[:, None, None] ** expo.clamp(min=0)[None], torch.zeros((), device=device,
+                                                                                           dtype=torch.float64))
+        L[:, :, 1:] *= torch.sqrt(1.0 - r * r)[:, None, None]
+        d = torch.rand((m, K), generator=g, device=device, dtype=torch.float64) * 90.0 + 10.0
+        vr_len = torch.randint(lo, hi + 1, (m, K), generator=g, device=device)
+        start = (torch.rand((m, K), generator=g, device=device, dtype=torch.float64)
+                 * (S - vr_len + 1).to(torch.float64)).floor().to(torch.int64)
+        mask = (sub[None, None, :] >= start[..., None]) & (sub[None, None, :] < (start + vr_len)[..., None])
+        re = torch.randn((m, K * S, Ms), generator=g, device=device, dtype=torch.float64)
+        im = torch.randn((m, K * S, Ms), generator=g, device=device, dtype=torch.float64)
+        Lt = L.transpose(1, 2).contiguous()
+        y = torch.complex(torch.bmm(re, Lt), torch.bmm(im, Lt)).reshape(m, K, S, Ms) / (2.0 ** 0.5)
+        y = y * mask[..., None]
+        beta = d ** -3.7 if gain == "literal" else (d / 10.0) ** -3.7
+        out[c0:c0 + m] = (beta.sqrt()[..., None, None] * y).reshape(m, K, M).to(torch.complex64)
+        del L, Lt, re, im, y
+    return out, rs
+

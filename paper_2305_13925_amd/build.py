@@ -26,11 +26,16 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["-std=c++17", "-fPIC", "-Wall", "-Werror", "-Wno-unused-result",
           f"-I{os.path.join(os.path.dirname(PKG), 'include')}"]
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# Per-file code generation choices. The FP64 kernels keep their matrix-core
+# accumulators in ordinary VGPRs: with accumulation registers the compiler
+# copied every accumulator between the two register files once per loop
+# iteration, and waited for the products before each copy.
+PER_FILE = {"refine.hip": ["-Xarch_device", "-mllvm=-amdgpu-mfma-vgpr-form=1"]}
 
 
 def _compile(src, opt):
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *COMMON, *DEVICE, opt, "-c", src, "-o", obj]
+    cmd = [HIPCC, *COMMON, *DEVICE, *PER_FILE.get(os.path.basename(src), []), opt, "-c", src, "-o", obj]
     if src.endswith(".hip"):
         cmd[1:1] = ["-x", "hip"]
     r = subprocess.run(cmd, capture_output=True, text=True)

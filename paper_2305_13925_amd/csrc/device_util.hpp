@@ -32,6 +32,12 @@ __device__ __forceinline__ float2 ld2(gptr<const float2> p) {
   const gfloat2 v = *reinterpret_cast<gptr<const gfloat2>>(p);
   return make_float2(v.x, v.y);
 }
+typedef double gdouble2 __attribute__((ext_vector_type(2)));
+// Complex FP64 entry p[0] through a global pointer (one 16-byte load).
+__device__ __forceinline__ double2 ld2d(gptr<const double2> p) {
+  const gdouble2 v = *reinterpret_cast<gptr<const gdouble2>>(p);
+  return make_double2(v.x, v.y);
+}
 typedef float gfloat4 __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ float4 ld4(gptr<const float4> p) {
   const gfloat4 v = *reinterpret_cast<gptr<const gfloat4>>(p);

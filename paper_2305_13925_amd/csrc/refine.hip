@@ -235,7 +235,7 @@ __global__ __launch_bounds__(256) void refine_step_kernel(RefineStepLaunch r) {
   if (threadIdx.x == 0 && r.steps) r.steps[L] = r.step;
   __syncthreads();
 
-  const double2* Ab = r.A64 + (int64_t)b * K * K;
+  gptr<const double2> Ab = as_global(r.A64 + (int64_t)b * K * K);
   const int ntr = (K + 15) >> 4;
   doublex4 qr[RT], qi[RT];
 #pragma unroll
@@ -244,32 +244,55 @@ __global__ __launch_bounds__(256) void refine_step_kernel(RefineStepLaunch r) {
     qi[t] = zero4d();
   }
   // A-operand of row tile t at complex step kk: conj(A[kk][rt * 16 + li]).
-  double2 acur[RT], anxt[RT];
-  auto load_a = [&](int k0, double2 (&dst)[RT]) {
-    const int kk = k0 + slot_k;
+  // Loads are unconditional (indices clamped into A) and masked where they are
+  // used, and two register buffers alternate, so each step's loads stay in
+  // flight under the previous step's products.
+  int ia_c[RT];
+  bool rv[RT];
 #pragma unroll
-    for (int t = 0; t < RT; ++t) {
-      const int ia = (w + 4 * t) * 16 + li;
-      dst[t] = (ia < K && kk < K) ? Ab[(int64_t)kk * K + ia] : make_double2(0.0, 0.0);
-    }
+  for (int t = 0; t < RT; ++t) {
+    const int ia = (w + 4 * t) * 16 + li;
+    rv[t] = ia < K;
+    ia_c[t] = min(ia, K - 1);
+  }
+  auto load_a = [&](int k0, double2 (&dst)[RT]) {
+    const int kk = min(k0 + slot_k, K - 1);
+#pragma unroll
+    for (int t = 0; t < RT; ++t) dst[t] = ld2d(Ab + (int64_t)kk * K + ia_c[t]);
   };
-  load_a(0, acur);
-  for (int k0 = 0; k0 < K; k0 += 2) {
-    if (k0 + 2 < K) load_a(k0 + 2, anxt);
+  // One complex step pair k0: operands from the staged values, then the stage
+  // is refilled with step k0 + 2 * kStages (clamped into A, so past the end it
+  // reloads a valid row and the join never waits), then the products.
+  constexpr int kStages = 4;
+  auto step = [&](double2 (&a)[RT], int k0) {
     const int kk = k0 + slot_k;
-    const double2 x = kk < K ? Xs[li][kk] : make_double2(0.0, 0.0);
-    const double xr = comp ? -x.y : x.x, xim = comp ? x.x : x.y;
-    // Every row tile is formed (rows beyond K read zeros): a branch around
-    // the products, though wave-uniform, makes the compiler move the
+    const bool kv = kk < K;
+    const double2 x = Xs[li][kv ? kk : 0];
+    const double xr = kv ? (comp ? -x.y : x.x) : 0.0;
+    const double xim = kv ? (comp ? x.x : x.y) : 0.0;
+    double av[RT];
+#pragma unroll
+    for (int t = 0; t < RT; ++t) av[t] = (rv[t] && kv) ? (comp ? -a[t].y : a[t].x) : 0.0;
+    load_a(k0 + 2 * kStages, a);
+    __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the products
+    // Every row tile is formed (rows beyond K are masked to zero): a branch
+    // around the products, though wave-uniform, makes the compiler move the
     // accumulators between register files around each one.
 #pragma unroll
     for (int t = 0; t < RT; ++t) {
-      const double av = comp ? -acur[t].y : acur[t].x;
-      qr[t] = mfma64(av, xr, qr[t]);
-      qi[t] = mfma64(av, xim, qi[t]);
+      qr[t] = mfma64(av[t], xr, qr[t]);
+      qi[t] = mfma64(av[t], xim, qi[t]);
     }
+  };
+  double2 st[kStages][RT];
 #pragma unroll
-    for (int t = 0; t < RT; ++t) acur[t] = anxt[t];
+  for (int u = 0; u < kStages; ++u) {
+    load_a(2 * u, st[u]);
+    __builtin_amdgcn_sched_barrier(0);  // stages issued in order: stage 0 arrives first
+  }
+  for (int k0 = 0; k0 < K; k0 += 2 * kStages) {
+#pragma unroll
+    for (int u = 0; u < kStages; ++u) step(st[u], k0 + 2 * u);
   }
 
   // Own rows of the result: rt*16 + q + 4*g, column j0 + li.

@@ -6,14 +6,17 @@ percentiles and throughput.
 
 Workload (the serving workload): arrivals at `rate` requests/s with exponential
 gaps; each request draws M from {256, ..., 4096}, K from {8, ..., 256} with
-K <= M/8 and 1-64 subcarriers, xi = K/10 (10 dB), tol 1e-6 or 16 iterations.
-Channels come from a device-side pool per (M, K) shape (64 instances of the
-single-instance channel model: 4 subarrays, visibility region of 2-4, r = 0.6),
-so that generating them does not dominate the run; a request of n subcarriers
-uses the first n pool instances. Latency is t_done - t_submit of the session
-clock; throughput counts the subcarrier precoders of requests that arrived
-after the warm-up, over the time from the first such arrival to the last
-completion.
+K <= M/8, 1-64 subcarriers and its own correlation coefficient r ~ U[0.3, 0.9];
+xi = K/10 (10 dB), tol 1e-6 or 16 iterations. Channels follow the
+single-instance model (4 subarrays, visibility region of 2-4) with literal or
+gain-normalised path loss. Drawing every request's channels while the stream
+runs would load the GPU more than the precoders do, so they are drawn before
+it: per (M, K) and per r band of width 0.1 a pool of 96 instances, each with
+its own r inside the band. A request takes n_sub consecutive instances of the
+pool of its own r, from an offset given by its seed. Latency is t_done -
+t_submit of the session clock; throughput counts the subcarrier precoders of
+requests that arrived after the warm-up, over the time from the first such
+arrival to the last completion.
 """
 
 from __future__ import annotations
@@ -32,25 +35,36 @@ if __package__ in (None, ""):
 from paper_2305_13925_amd import binding as bd  # noqa: E402
 
 
+R_BANDS = 6          # r ~ U[0.3, 0.9] in bands of width 0.1
+POOL = 96            # instances per (M, K, band) pool; windows of up to 64
+
+
+def r_band(r):
+    return min(R_BANDS - 1, max(0, int((r - 0.3) / 0.1)))
+
+
 def run_serving(session, rate_hz=2000.0, warmup_s=1.0, measure_s=10.0, seed=0, tol=1e-6, max_iter=16,
-                precision=bd.GRAM_FP32, n_out=4, progress=None):
+                precision=bd.GRAM_FP32, n_out=8, progress=None, gain="literal"):
     import torch
-    from channelgen import device_pool, serving_requests
+    from channelgen import device_pool_r, serving_requests
 
     reqs = serving_requests(rate_hz, warmup_s + measure_s, seed)
     shapes = sorted({(q["M"], q["K"]) for q in reqs})
     pools, outs = {}, {}
     for i, (M, K) in enumerate(shapes):
-        pools[(M, K)] = device_pool(M, 4, K, 0.6, (2, 4), 64, seed * 1000 + i)
-        outs[(M, K)] = [torch.empty_like(pools[(M, K)]) for _ in range(n_out)]
+        for band in range(R_BANDS):
+            lo = 0.3 + 0.1 * band
+            pools[(M, K, band)], _ = device_pool_r(M, 4, K, (lo, lo + 0.1), (2, 4), POOL,
+                                                   seed * 100003 + i * R_BANDS + band, gain=gain)
+        outs[(M, K)] = [torch.empty((64, K, M), dtype=torch.complex64, device="cuda") for _ in range(n_out)]
     torch.cuda.synchronize()
     # one request per shape first, so kernel code objects are loaded before timing
     for (M, K) in shapes:
-        t = bd.jacpcg_submit(session, pools[(M, K)][:1], outs[(M, K)][0][:1], K / 10.0, tol=tol,
+        t = bd.jacpcg_submit(session, pools[(M, K, 0)][:1], outs[(M, K)][0][:1], K / 10.0, tol=tol,
                              max_iter=max_iter, precision=precision)
         bd.jacpcg_wait(session, t)
     if progress:
-        progress(f"serving: {len(reqs)} requests over {len(shapes)} shapes, pools ready")
+        progress(f"serving ({gain}): {len(reqs)} requests over {len(shapes)} shapes, pools ready")
 
     tickets = []
     t0 = time.perf_counter()
@@ -58,9 +72,10 @@ def run_serving(session, rate_hz=2000.0, warmup_s=1.0, measure_s=10.0, seed=0, t
         delay = t0 + q["t"] - time.perf_counter()
         if delay > 0:
             time.sleep(delay)
-        key = (q["M"], q["K"])
         n = q["n_sub"]
-        t = bd.jacpcg_submit(session, pools[key][:n], outs[key][i % n_out][:n], q["xi"], tol=tol,
+        off = q["seed"] % (POOL - n + 1)
+        H = pools[(q["M"], q["K"], r_band(q["r"]))][off:off + n]
+        t = bd.jacpcg_submit(session, H, outs[(q["M"], q["K"])][i % n_out][:n], q["xi"], tol=tol,
                              max_iter=max_iter, precision=precision, user_tag=i)
         tickets.append(t)
     results = [bd.jacpcg_wait(session, t) for t in tickets]
@@ -96,6 +111,8 @@ def run_serving(session, rate_hz=2000.0, warmup_s=1.0, measure_s=10.0, seed=0, t
         "statuses": {str(k): v for k, v in statuses.items()},
         "wall_s": wall,
         "max_iters": int(max(r["max_iters"] for _, r in meas)),
+        "mean_max_iters": float(np.mean([r["max_iters"] for _, r in meas])),
+        "gain": gain,
     }
 
 
@@ -106,9 +123,10 @@ def main(argv=None):
     ap.add_argument("--seconds", type=float, default=10.0)
     ap.add_argument("--budget-gb", type=float, default=64.0)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--gain", default="literal", choices=["literal", "normalised"])
     a = ap.parse_args(argv)
     with bd.Session(0, hbm_budget_bytes=int(a.budget_gb * 2 ** 30)) as s:
-        out = run_serving(s, a.rate, a.warmup, a.seconds, a.seed,
+        out = run_serving(s, a.rate, a.warmup, a.seconds, a.seed, gain=a.gain,
                           progress=lambda m: print(m, file=sys.stderr, flush=True))
     print(json.dumps(out), flush=True)
 

@@ -62,3 +62,18 @@ def test_xi_rule_and_serving_stream():
         assert 1 <= q["n_sub"] <= 64 and 0.3 <= q["r"] <= 0.9
     gaps = np.diff([q["t"] for q in reqs])
     assert abs(gaps.mean() - 1 / 2000) < 0.15 / 2000
+
+
+def test_device_pool_r_draws_each_instance_at_its_own_r():
+    # per-instance correlation: the lag-1 antenna correlation of an instance
+    # drawn at r is r (one subarray, every user visible, many users)
+    import torch
+    from channelgen import device_pool_r
+    H, rs = device_pool_r(512, 1, 64, (0.3, 0.9), (1, 1), 4, 5, device="cpu", gain="normalised", chunk=3)
+    assert H.shape == (4, 64, 512) and H.dtype == torch.complex64
+    r = rs.numpy()
+    assert np.all((r >= 0.3) & (r <= 0.9)) and np.ptp(r) > 0.05
+    for b in range(4):
+        x = H[b].numpy().astype(np.complex128)
+        c = np.sum(x[:, 1:] * np.conj(x[:, :-1])) / np.sum(np.abs(x[:, :-1]) ** 2)
+        assert abs(c.real - r[b]) < 0.03 and abs(c.imag) < 0.03, (b, c, r[b])
