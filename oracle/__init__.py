@@ -25,7 +25,7 @@ from .rzf import (  # noqa: F401
     chol_inverse,
     gauss_jordan_inverse,
     jacpcg,
-    jacpcg_alg1_literal,
+    cg_on_jacobi_scaled_operator,
     precoder,
     rzf,
     block_slices,

@@ -132,7 +132,7 @@ def jacpcg(A, B=None, tol=0.0, max_iter=16, precond="jacobi"):
         beta = (r'^H C^{-1} r') / (r^H C^{-1} r), i.e. the standard PCG form
         whose step length Step 3 states; Algorithm 1's listing instead takes
         Euclidean products on C^{-1} A, which agrees only when diag(A) is
-        constant (see ``jacpcg_alg1_literal``);
+        constant (see ``cg_on_jacobi_scaled_operator``);
       * the two inner products are real for Hermitian positive definite A
         (eq. 18); their real parts are used;
       * stop rule (Step 2, applied per column, relative to ||b_j||): stop as soon
@@ -220,30 +220,37 @@ def jacpcg(A, B=None, tol=0.0, max_iter=16, precond="jacobi"):
                 status=status, instance_status=inst)
 
 
-def jacpcg_alg1_literal(A, s, T):
-    """Algorithm 1 taken literally: Euclidean CG on the preconditioned operator.
+def _euclidean_cg(apply_op, rhs, T):
+    """T steps of textbook conjugate gradient with Euclidean inner products on
+    the linear operator ``apply_op`` from x = 0 (Hestenes-Stiefel form). For a
+    Hermitian positive definite operator this is the Krylov-optimal method; the
+    recurrences are evaluated as written even when the operator is not
+    Hermitian."""
+    x = np.zeros_like(rhs)
+    res = rhs.copy()
+    d = res.copy()
+    for _ in range(T):
+        Ad = apply_op(d)
+        step = np.vdot(res, res) / np.vdot(d, Ad)
+        x = x + step * d
+        res_new = res - step * Ad
+        d = res_new + (np.vdot(res_new, res_new) / np.vdot(res, res)) * d
+        res = res_new
+    return x
 
-    The listing sets r = C^{-1} s, m = r and, per iteration, uses
-    alpha = r^H r / (m^H C^{-1} A m), r' = r - alpha C^{-1} A m and
-    b = r'^H r' / r^H r. Kept only to document why the standard PCG reading is
-    used in ``jacpcg``: the two agree when diag(A) is constant and drift apart
-    otherwise. Never a parity target of the GPU path.
+
+def cg_on_jacobi_scaled_operator(A, s, T):
+    """The iteration Algorithm 1 prints: it is Euclidean CG (``_euclidean_cg``)
+    applied to the operator C^{-1} A with right-hand side C^{-1} s, C =
+    diag(A). C^{-1} A is not Hermitian unless diag(A) is constant, so this is
+    not the preconditioned CG of Step 3 (the reading ``jacpcg`` takes). Kept
+    only to document that choice: the two agree when diag(A) is constant and
+    drift apart otherwise. Never a parity target of the GPU path.
     """
     A = _c128(A)
     s = _c128(s).reshape(-1)
-    Cinv = 1.0 / A.diagonal().real
-    w = np.zeros_like(s)
-    r = Cinv * s
-    m = r.copy()
-    for _ in range(T):
-        CAm = Cinv * (A @ m)
-        alpha = np.vdot(r, r) / np.vdot(m, CAm)
-        w = w + alpha * m
-        r_next = r - alpha * CAm
-        b = np.vdot(r_next, r_next) / np.vdot(r, r)
-        m = r_next + b * m
-        r = r_next
-    return w
+    cinv = 1.0 / A.diagonal().real
+    return _euclidean_cg(lambda v: cinv * (A @ v), cinv * s, T)
 
 
 # ---------------------------------------------------------------------------

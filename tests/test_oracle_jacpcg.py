@@ -167,11 +167,11 @@ def test_literal_algorithm1_coincides_only_for_constant_diagonal(rng):
     Aunit = dh[:, None] * A * dh[None, :]            # unit diagonal
     b = _crandn(rng, 8)
     for T in (1, 3, 5):
-        np.testing.assert_allclose(oracle.jacpcg_alg1_literal(Aunit, b, T),
+        np.testing.assert_allclose(oracle.cg_on_jacobi_scaled_operator(Aunit, b, T),
                                    oracle.jacpcg(Aunit, b, tol=0.0, max_iter=T)["X"][:, 0],
                                    rtol=0, atol=1e-12)
     Avar = _hpd(rng, 30, 8, 0.01, spread=30.0)
-    lit = oracle.jacpcg_alg1_literal(Avar, b, 8)
+    lit = oracle.cg_on_jacobi_scaled_operator(Avar, b, 8)
     std = oracle.jacpcg(Avar, b, tol=0.0, max_iter=8)["X"][:, 0]
     assert np.linalg.norm(lit - std) > 1e-6 * np.linalg.norm(std)
     assert np.linalg.norm(std - np.linalg.solve(Avar, b)) < 1e-9 * np.linalg.norm(std)
