@@ -51,11 +51,12 @@ void Scheduler::start() {
   for (auto& sl : slots_) {
     (void)hipSetDevice(s_->device);
     (void)hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
-    (void)hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
+    // A blocking-sync event: its waiter sleeps until the batch completes.
+    (void)hipEventCreateWithFlags(&sl.done, hipEventDisableTiming | hipEventBlockingSync);
   }
   running_ = true;
   sched_thread_ = std::thread([this] { scheduler_loop(); });
-  comp_thread_ = std::thread([this] { completion_loop(); });
+  for (size_t i = 0; i < slots_.size(); ++i) slot_threads_.emplace_back([this, i] { completion_loop(i); });
 }
 
 void Scheduler::stop() {
@@ -68,7 +69,9 @@ void Scheduler::stop() {
   cv_comp_.notify_all();
   cv_done_.notify_all();
   if (sched_thread_.joinable()) sched_thread_.join();
-  if (comp_thread_.joinable()) comp_thread_.join();
+  for (auto& t : slot_threads_)
+    if (t.joinable()) t.join();
+  slot_threads_.clear();
   (void)hipSetDevice(s_->device);
   for (auto& kv : reqs_)
     if (kv.second.ready) give_event(kv.second.ready);
@@ -298,7 +301,7 @@ void Scheduler::scheduler_loop() {
         launched = true;
       }
     }
-    if (launched) cv_comp_.notify_one();
+    if (launched) cv_comp_.notify_all();
   }
 }
 
@@ -466,41 +469,37 @@ void Scheduler::finish(Slot& sl) {
   --inflight_;
 }
 
-void Scheduler::completion_loop() {
+// One completion thread per slot: it sleeps until its slot is armed, then in
+// hipEventSynchronize on the slot's blocking-sync event, and publishes the
+// batch's results as soon as the event completes (no polling).
+void Scheduler::completion_loop(size_t i) {
   (void)hipSetDevice(s_->device);
   std::unique_lock<std::mutex> lk(mu_);
   while (true) {
-    cv_comp_.wait(lk, [&] { return inflight_ > 0 || stop_; });
-    if (stop_ && inflight_ == 0) break;
-    bool any = false;
-    for (auto& sl : slots_) {
-      if (!sl.armed) continue;
-      const hipError_t q = hipEventQuery(sl.done);
-      if (q == hipErrorNotReady) continue;
-      any = true;
-      if (q != hipSuccess) {
-        for (uint64_t t : sl.members) {
-          Req& r = reqs_.at(t);
-          r.state = kDone;
-          r.status = JACPCG_E_HIP;
-          r.t_done = now_us();
-        }
-        used_ -= sl.bytes;
-        sl.busy = false;
-        sl.armed = false;
-        --inflight_;
-      } else {
-        finish(sl);
+    cv_comp_.wait(lk, [&] { return stop_ || slots_[i].armed; });
+    Slot& sl = slots_[i];
+    if (!sl.armed) break;  // stopping, nothing in flight on this slot
+    const hipEvent_t ev = sl.done;
+    lk.unlock();
+    const hipError_t q = hipEventSynchronize(ev);
+    lk.lock();
+    if (q != hipSuccess) {
+      (void)hipGetLastError();
+      for (uint64_t t : sl.members) {
+        Req& r = reqs_.at(t);
+        r.state = kDone;
+        r.status = JACPCG_E_HIP;
+        r.t_done = now_us();
       }
-    }
-    if (any) {
-      cv_done_.notify_all();
-      cv_sched_.notify_one();
+      used_ -= sl.bytes;
+      sl.busy = false;
+      sl.armed = false;
+      --inflight_;
     } else {
-      lk.unlock();
-      std::this_thread::sleep_for(std::chrono::microseconds(20));
-      lk.lock();
+      finish(sl);
     }
+    cv_done_.notify_all();
+    cv_sched_.notify_one();
   }
 }
 

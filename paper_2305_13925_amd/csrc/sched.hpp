@@ -59,7 +59,7 @@ class Scheduler {
     char* host = nullptr;  // pinned staging
     size_t host_bytes = 0;
     bool busy = false;   // reserved by the scheduler thread
-    bool armed = false;  // launched and its completion event recorded: the completion thread may finish it
+    bool armed = false;  // launched and its completion event recorded: its completion thread may finish it
     std::vector<uint64_t> members;
     std::vector<int> inst_begin;  // first instance of each member in the batch
     int instances = 0;
@@ -71,7 +71,7 @@ class Scheduler {
 
   void start();
   void scheduler_loop();
-  void completion_loop();
+  void completion_loop(size_t slot);
   int launch(Slot& slot, const std::vector<uint64_t>& members, const std::vector<jacpcg_request>& rq,
              const std::vector<hipEvent_t>& ready);
   hipEvent_t take_event();             // from the pool, or a new one (lock held)
@@ -90,7 +90,8 @@ class Scheduler {
   size_t used_ = 0;
   bool running_ = false, stop_ = false;
   int inflight_ = 0;
-  std::thread sched_thread_, comp_thread_;
+  std::thread sched_thread_;
+  std::vector<std::thread> slot_threads_;  // one completion thread per slot
 };
 
 }  // namespace jacpcg
