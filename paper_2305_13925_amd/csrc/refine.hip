@@ -7,6 +7,8 @@
 // v_mfma_f64_16x16x4_f64 layout: A-operand lane l holds A[l%16][l/16],
 // B-operand B[l/16][l%16], result register r of lane l is D[l/16 + 4r][l%16].
 // The four k slots carry two complex terms as (Re, Im) pairs.
+#include <type_traits>
+
 #include "device_util.hpp"
 
 namespace jacpcg {
@@ -113,31 +115,54 @@ __global__ __launch_bounds__(256) void gram64_kernel(Gram64Launch g) {
     accR[c] = zero4d();
     accI[c] = zero4d();
   }
-  const int opj = same ? 0 : 1;
-  const int c0 = same ? w : 0;  // first tile of this wave's strip on or above the diagonal (the rest is discarded)
-  const int nst = (g.M + kG64Ant - 1) / kG64Ant;
-  load_stage(0);
-  store_stage();
-  __syncthreads();
-  for (int s2 = 0; s2 < nst; ++s2) {
-    if (s2 + 1 < nst) load_stage((s2 + 1) * kG64Ant);
+  // The products of one stage for NT tiles (row tile R[t] of operand block 0,
+  // column tile C[t] of operand block OPJ: 1 off the diagonal, 0 on it). Called with compile-time tile lists, so
+  // every LDS offset is static and every product is unconditional.
+  auto products = [&](auto nt_tag, auto opj_tag, const int (&R)[4], const int (&C)[4]) {
+    constexpr int NT = decltype(nt_tag)::value;
+    constexpr int OPJ = decltype(opj_tag)::value;
 #pragma unroll 2  // full unrolling hoists every operand: one wave per SIMD
     for (int p = 0; p < kG64Ant / 2; ++p) {
       // k slot q: antenna 2p + slot_m, component comp (Re, Im pairs).
-      const float2 a = Hs[0][16 * w + li][2 * p + slot_m];
-      const double av = comp ? (double)a.y : (double)a.x;
-      // Every wave forms all four tiles: a per-tile branch here, though
-      // wave-uniform, made the compiler copy the accumulators out of and back
-      // into the matrix-core registers around each product and wait for it.
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const float2 h = Hs[opj][16 * c + li][2 * p + slot_m];
+      for (int c = 0; c < NT; ++c) {
+        const float2 a = Hs[0][16 * R[c] + li][2 * p + slot_m];
+        const float2 h = Hs[OPJ][16 * C[c] + li][2 * p + slot_m];
+        const double av = comp ? (double)a.y : (double)a.x;
         const double br = comp ? (double)h.y : (double)h.x;
         const double bim = comp ? -(double)h.x : (double)h.y;
         accR[c] = mfma64(av, br, accR[c]);
         accI[c] = mfma64(av, bim, accI[c]);
       }
     }
+  };
+  // Tiles of each wave. Off the diagonal: row tile w against the four column
+  // tiles. On it: the ten upper tiles (r <= c) dealt 3, 3, 2, 2 over the waves,
+  // so no tile below the diagonal is formed.
+  constexpr int kDiagR[4][4] = {{0, 0, 0, 0}, {0, 1, 1, 0}, {1, 2, 0, 0}, {2, 3, 0, 0}};
+  constexpr int kDiagC[4][4] = {{0, 1, 2, 0}, {3, 1, 2, 0}, {3, 2, 0, 0}, {3, 3, 0, 0}};
+  const int offR[4] = {w, w, w, w};
+  constexpr int offC[4] = {0, 1, 2, 3};
+  const int ntile = same ? (w < 2 ? 3 : 2) : 4;
+  auto stage = [&]() {
+    if (!same) {
+      products(std::integral_constant<int, 4>{}, std::integral_constant<int, 1>{}, offR, offC);
+    } else {
+      switch (w) {  // wave-uniform
+        case 0: products(std::integral_constant<int, 3>{}, std::integral_constant<int, 0>{}, kDiagR[0], kDiagC[0]); break;
+        case 1: products(std::integral_constant<int, 3>{}, std::integral_constant<int, 0>{}, kDiagR[1], kDiagC[1]); break;
+        case 2: products(std::integral_constant<int, 2>{}, std::integral_constant<int, 0>{}, kDiagR[2], kDiagC[2]); break;
+        default: products(std::integral_constant<int, 2>{}, std::integral_constant<int, 0>{}, kDiagR[3], kDiagC[3]); break;
+      }
+    }
+  };
+  const int nst = (g.M + kG64Ant - 1) / kG64Ant;
+  load_stage(0);
+  store_stage();
+  __syncthreads();
+  for (int s2 = 0; s2 < nst; ++s2) {
+    if (s2 + 1 < nst) load_stage((s2 + 1) * kG64Ant);
+    stage();
     __syncthreads();  // every wave is done with this stage
     if (s2 + 1 < nst) {
       store_stage();
@@ -145,18 +170,21 @@ __global__ __launch_bounds__(256) void gram64_kernel(Gram64Launch g) {
     }
   }
 
-  // Element (row q + 4r, column li) of tile (w, c) sits in register r. Each
-  // entry strictly above the diagonal of A is written with its conjugate
-  // mirror, the diagonal gets xi and an exactly zero imaginary part, and
-  // entries below the diagonal of a diagonal block are left to their mirror.
+  // Element (row q + 4r, column li) of a tile sits in register r. Each entry
+  // strictly above the diagonal of A is written with its conjugate mirror, the
+  // diagonal gets xi and an exactly zero imaginary part; entries below the
+  // diagonal of a diagonal tile are left to their mirror.
   double2* Ab = g.A64 + (int64_t)b * g.K * g.K;
+  const int wq = min(w, 3);
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
-    if (c < c0) continue;
+    if (c >= ntile) continue;
+    const int tr = same ? kDiagR[wq][c] : w;
+    const int tc = same ? kDiagC[wq][c] : c;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int gi = bi * kG64Rows + 16 * w + q + 4 * r;
-      const int gj = bj * kG64Rows + 16 * c + li;
+      const int gi = bi * kG64Rows + 16 * tr + q + 4 * r;
+      const int gj = bj * kG64Rows + 16 * tc + li;
       if (gi >= g.K || gj >= g.K || gi > gj) continue;
       const double re = accR[c][r], im = accI[c][r];
       if (gi == gj) {

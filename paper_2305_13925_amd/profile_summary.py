@@ -33,7 +33,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 KERNEL_SOURCES = ["paper_2305_13925_amd/csrc/gram.hip", "paper_2305_13925_amd/csrc/pcg.hip",
                   "paper_2305_13925_amd/csrc/precoder.hip", "paper_2305_13925_amd/csrc/device_util.hpp",
                   "paper_2305_13925_amd/csrc/common.hpp"]
-PHASE_PREFIX = {"gram": "gram_", "solve": "pcg_", "epilogue": "precoder_"}
+PHASE_PREFIX = {"gram": "gram_", "solve": "pcg_", "epilogue": "precoder_", "gram64": "gram64_",
+                "refine_step": "refine_step_"}
 
 
 def short_name(name):
