@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--no-rows", action="store_true", help="skip the adjacent rows (transmit, block, SINR)")
     ap.add_argument("--rows-only", default=None, choices=["precision", "stress"],
                     help="only run one workload's rows (for per-workload profiles) and print them as JSON")
+    ap.add_argument("--calibrate-peaks", action="store_true",
+                    help="only measure the matrix-core peaks (FP32, BF16, FP64, int8) with register-only loops")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for the HBM traffic counters)")
     return ap.parse_args()
@@ -573,6 +575,13 @@ def main():
     a = parse()
     if a.calibrate_copy:
         return calibrate_copy()
+    if a.calibrate_peaks:
+        import torch
+        from paper_2305_13925_amd import binding as bd
+        with bd.Session(0) as s:
+            print(json.dumps({"mfma_peaks": bd.mfma_peaks(s, torch.cuda.current_stream()),
+                              "unit": "TFLOP/s (int8: TOP/s)"}), flush=True)
+        return 0
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {a.gpus}): instances are independent and a "
               "multi-GPU run would shard them without communication.", file=sys.stderr)

@@ -142,6 +142,14 @@ int jacpcg_session_set_graphs(jacpcg_session* s, int enable);
  * stay independent of batch composition. */
 int jacpcg_autotune(jacpcg_session* s, void* stream, int batch, int M, int K, int precision, int flags);
 
+/* Matrix-core peaks measured on the session's device: register-only loops of
+ * independent MFMA chains (two waves per SIMD on every compute unit), timed
+ * with HIP events on `stream`. tflops (host, 4 doubles) receives FP32
+ * (32x32x2), BF16 (32x32x16), FP64 (16x16x4) TFLOP/s and int8 (32x32x32)
+ * TOP/s. A calibration aid: it allocates a small output buffer and
+ * synchronises `stream`. Errors: E_INVALID_ARG (NULL), E_HIP. */
+int jacpcg_mfma_peaks(jacpcg_session* s, void* stream, double* tflops);
+
 /* ---- the three steps ---------------------------------------------------- */
 
 /* Regularised Gram (eq. 7): A_b = H_b^H H_b + xi I_K for b < batch.

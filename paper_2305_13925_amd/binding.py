@@ -123,6 +123,8 @@ def _declare(lib):
                                        C.c_int, C.c_double, _vp, C.c_int64, C.c_int64, C.POINTER(JacpcgStats)]
     lib.rzf_sinr.argtypes = [_vp, _vp, C.c_int, C.c_int, C.c_int, _vp, C.c_int64, C.c_int64, _vp, C.c_int64,
                              C.c_int64, C.c_double, _vp, _vp]
+    lib.jacpcg_mfma_peaks.argtypes = [_vp, _vp, C.POINTER(C.c_double)]
+    lib.jacpcg_mfma_peaks.restype = C.c_int
     lib.jacpcg_session_set_graphs.argtypes = [_vp, C.c_int]
     lib.jacpcg_autotune.argtypes = [_vp, _vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]
     lib.jacpcg_submit.argtypes = [_vp, C.POINTER(JacpcgRequest), C.POINTER(C.c_uint64)]
@@ -501,3 +503,12 @@ def exported_symbols():
 def to_numpy_instance(t):
     """Host copy of one [n, rows] column-major instance as a rows x n complex128 matrix."""
     return np.asarray(t.detach().cpu().numpy()).T.astype(np.complex128)
+
+
+def mfma_peaks(session, stream=None):
+    """Measured matrix-core peaks of the session's device:
+    {"fp32": TFLOP/s, "bf16": TFLOP/s, "fp64": TFLOP/s, "int8": TOP/s}."""
+    out = (C.c_double * 4)()
+    _check(lib().jacpcg_mfma_peaks(session.handle, _stream(stream), out))
+    return dict(zip(("fp32", "bf16", "fp64", "int8"), (round(v, 1) for v in out)))
+

@@ -69,6 +69,7 @@ int run_rzf_noalloc(jacpcg_session* s, hipStream_t st, int batch, int M, int K, 
                     bool precond_none, bool split_epilogue, float2* W, int64_t ldw, int64_t stride_w,
                     int32_t* status) {
   if (s->device < 0 || s->device >= kMaxDevices) return set_error(JACPCG_E_NO_DEVICE, "device out of range");
+  const PhaseRange range("rzf_precoder_noalloc");
   char* base = nullptr;
   {
     std::lock_guard<std::mutex> lk(g_mu);

@@ -307,6 +307,7 @@ void Scheduler::scheduler_loop() {
 
 int Scheduler::launch(Slot& sl, const std::vector<uint64_t>& members, const std::vector<jacpcg_request>& rq,
                       const std::vector<hipEvent_t>& ready) {
+  const PhaseRange range("serve batch");
   (void)hipSetDevice(s_->device);
   const jacpcg_request& r0 = rq[0];
   const int M = r0.M, K = r0.K;

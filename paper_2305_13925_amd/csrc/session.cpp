@@ -225,7 +225,10 @@ int jacpcg_session::run_rzf(hipStream_t st, int batch, int M, int K, const float
   // enqueued, and each column stops taking corrections once its FP64 residual
   // meets refine_tol (later launches find nothing left to do for it).
   auto enqueue_all = [&](hipStream_t q, bool timed_run) -> hipError_t {
+    static const char* const kPhaseName[JACPCG_NUM_PHASES] = {"gram", "solve", "epilogue", "gram64",
+                                                             "refine step"};
     auto run = [&](int phase, auto&& launch) -> hipError_t {
+      const PhaseRange range(kPhaseName[phase]);
       return timed_run ? timed(q, phase, launch) : launch();
     };
     hipError_t e = hipSuccess;
@@ -378,6 +381,7 @@ int jacpcg_session::run_rzf(hipStream_t st, int batch, int M, int K, const float
 
   // Repeated calls with identical arguments replay one captured HIP graph
   // (captured on a side stream, launched on the caller's stream).
+  const PhaseRange call_range(refine ? "rzf_precoder (refined)" : "rzf_precoder");
   bool launched = false;
   if (use_graphs && !profiling) {
     const uint64_t key = graph_key({(uint64_t)batch, (uint64_t)M, (uint64_t)K, (uint64_t)nrhs,

@@ -10,12 +10,23 @@
 #include <string>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "../../include/jacpcg.h"
 #include "common.hpp"
 #include "sched.hpp"
 #include "tuner.hpp"
 
 namespace jacpcg {
+
+// A roctx range around the host-side enqueue of one call or phase: named
+// ranges in a rocprofv3 --marker-trace, and a no-op without a profiler.
+struct PhaseRange {
+  explicit PhaseRange(const char* name) { roctxRangePushA(name); }
+  ~PhaseRange() { roctxRangePop(); }
+  PhaseRange(const PhaseRange&) = delete;
+  PhaseRange& operator=(const PhaseRange&) = delete;
+};
 
 // Two-phase workspace plan: offsets are taken first, the arena is sized once,
 // then offsets become device pointers.

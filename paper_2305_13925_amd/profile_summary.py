@@ -11,6 +11,9 @@
         kernel of N bytes read and N bytes written. Writes <out>.json (read by
         bench.py; tied to the sha256 of the kernel sources) and <out>.md.
 
+    python -m paper_2305_13925_amd.profile_summary markers <trace dir> --cmd C --out F
+        host-side roctx ranges (per call and per phase) from a --marker-trace run
+
     python -m paper_2305_13925_amd.profile_summary busy <pmc dir> --cmd C --out profiles/mfma_busy
         matrix-core utilisation and clock of the Gram, PCG and precoder
         kernels from a pass with GRBM_GUI_ACTIVE and SQ_VALU_MFMA_BUSY_CYCLES:
@@ -183,6 +186,29 @@ def busy(a):
     print("\n".join(lines))
 
 
+def markers(a):
+    """Host-side roctx ranges of the library (one per call and per phase
+    enqueued kernel by kernel): count and mean duration per range name."""
+    files = glob.glob(os.path.join(a.dir, "**", "*marker_api_trace.csv"), recursive=True)
+    if not files:
+        raise FileNotFoundError(f"no marker_api_trace.csv under {a.dir}")
+    d = collections.defaultdict(list)
+    for r in csv.DictReader(open(files[0])):
+        d[r["Function"]].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    lines = ["# roctx ranges of the library (host side)\n",
+             "Command (run from the repository root on one MI355X):\n", "```", a.cmd, "```\n",
+             "Each call of the library opens a range named for the call; when its kernels are enqueued one by one "
+             "(graph capture, eager launches with per-kernel timing) each phase opens its own range inside it. "
+             "A replayed graph shows only the call's range. Durations are host time spent enqueueing.\n",
+             "| range | count | mean us | max us |", "|---|---|---|---|"]
+    for name, v in sorted(d.items(), key=lambda kv: -len(kv[1])):
+        lines.append(f"| {name} | {len(v)} | {sum(v) / len(v):.1f} | {max(v):.1f} |")
+    text = "\n".join(lines) + "\n"
+    if a.out:
+        open(a.out, "w").write(text)
+    print(text)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd_name", required=True)
@@ -201,9 +227,15 @@ def main(argv=None):
     b.add_argument("dir")
     b.add_argument("--cmd", required=True)
     b.add_argument("--out", required=True)
+    m = sub.add_parser("markers")
+    m.add_argument("dir")
+    m.add_argument("--cmd", required=True)
+    m.add_argument("--out")
     a = ap.parse_args(argv)
     if a.cmd_name == "busy":
         return busy(a)
+    if a.cmd_name == "markers":
+        return markers(a)
     if a.cmd_name == "trace":
         text = trace_table(a.csv, a.title, a.cmd)
         if a.out:

@@ -254,3 +254,11 @@ def test_fp64_rounded_gram_needs_refinement():
     rc = L.rzf_precoder(*common, bd.GRAM_FP64_ROUNDED | bd.REFINE_FP64, 0, 1e-10, FAKE, 64, 64 * 16, NULL, NULL,
                         NULL)
     assert rc == bd.E_INVALID_ARG and "session" in _err()
+
+
+def test_phase_ranges_and_peak_probe_are_linked():
+    # the library marks its phases with roctx ranges (rocprofv3 --marker-trace)
+    out = subprocess.run(["nm", "-D", "--undefined-only", bd.LIB_PATH], capture_output=True, text=True).stdout
+    assert "roctxRangePushA" in out and "roctxRangePop" in out
+    # the matrix-core probe validates its arguments on the host
+    assert L.jacpcg_mfma_peaks(NULL, NULL, NULL) == bd.E_INVALID_ARG
