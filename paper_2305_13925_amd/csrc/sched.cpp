@@ -260,14 +260,22 @@ void Scheduler::scheduler_loop() {
       size_t bytes = 0;
       const double ta = now_us();
       for (size_t i : grp) {
+        // The lock was released around the previous group's launch: a request
+        // of this group may have been cancelled (and even collected) since
+        // the admission list was made. Only requests still queued are admitted.
         const uint64_t t = pend[i].ticket;
+        auto it = reqs_.find(t);
+        if (it == reqs_.end() || it->second.state != kQueued) continue;
+        const auto qi = std::find(queue_.begin(), queue_.end(), t);
+        if (qi == queue_.end()) continue;
+        queue_.erase(qi);
         members.push_back(t);
-        Req& q = reqs_.at(t);
+        Req& q = it->second;
         q.state = kRunning;
         q.t_admit = ta;
         bytes += q.bytes;
-        queue_.erase(std::find(queue_.begin(), queue_.end(), t));
       }
+      if (members.empty()) continue;
       used_ += bytes;
       free_slot->busy = true;  // reserved; the completion thread ignores it until armed
       free_slot->bytes = bytes;
