@@ -47,6 +47,7 @@ def parse():
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="measured seconds of the Poisson serving stream (0: skip)")
     ap.add_argument("--no-rows", action="store_true", help="skip the adjacent rows (transmit, block, SINR)")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default launch choices (no autotuning)")
     ap.add_argument("--rows-only", default=None, choices=["precision", "stress"],
                     help="only run one workload's rows (for per-workload profiles) and print them as JSON")
     ap.add_argument("--calibrate-peaks", action="store_true",
@@ -622,6 +623,17 @@ def main():
         bd.rzf_precoder(sess, Hs[i % 2], xi, power=1.0, tol=0.0, max_iter=T, precision=prec, flags=flags, W=W,
                         stream=stream)
 
+    # Launch choices for the headline shape from the session's autotuner.
+    tuned = None
+    if not a.no_tune:
+        sess.autotune(256, M, K, prec, flags, stream=stream)
+        split = 0 if flags & bd.EPILOGUE_FP32 else 3
+        tuned = {"gram_waves": sess.tune_get("gram_waves", M, K, prec),
+                 "pcg_a_source": sess.tune_get("pcg_a_source", 0, K, 0),
+                 "precoder_nj": sess.tune_get("precoder_nj", M, K, split),
+                 "precoder_mtiles": sess.tune_get("precoder_mtiles", M, K, split)}
+        progress(f"autotuned launch choices: {tuned}")
+
     # Timed region: the product's default launch path. Repeated calls with the
     # same arguments replay the session's captured HIP graph; profiling is off.
     for i in range(a.warmup):
@@ -796,6 +808,7 @@ def main():
         "speedup_vs_plain": round(value / plain_value, 2) if plain_value else None,
         "plain_vs_batched_rel_diff": same,
         "launch_path": "graph replay (the default for repeated calls), profiling off",
+        "tuned_choices": tuned,
         "eager_profiled_ms_per_step": round(eager_ms, 4),
         "eager_profiled_value": round(batch / (eager_ms / 1e3), 1),
         "tol_1e-5": {"ms_per_step": round(tol_ms, 4), "value": round(batch / (tol_ms / 1e3), 1),

@@ -134,12 +134,13 @@ int jacpcg_session_phase_times(jacpcg_session* s, double* ms_out, int64_t* launc
  * the replay. */
 int jacpcg_session_set_graphs(jacpcg_session* s, int enable);
 
-/* Autotune the launch choices for one shape: times the Gram and precoder
- * launch variants on `batch` synthetic instances of M x K (device memory from
- * the session workspace) and keeps the fastest per (M, K, precision); the
- * choices are saved to the session's tune cache file at destroy. Synchronises
- * `stream`. Choices depend only on the shape, never on the batch, so results
- * stay independent of batch composition. */
+/* Autotune the launch choices for one shape: times every value of each knob
+ * of jacpcg_tune_set that applies (Gram waves; where the solver keeps A for
+ * K <= 64; precoder column tiles and antenna blocks) on `batch` synthetic
+ * instances of M x K (device memory from the session workspace) and keeps the
+ * fastest; the choices are saved to the session's tune cache file at destroy.
+ * Synchronises `stream`. Choices depend only on the shape, never on the
+ * batch, so results stay independent of batch composition. */
 int jacpcg_autotune(jacpcg_session* s, void* stream, int batch, int M, int K, int precision, int flags);
 
 /* Matrix-core peaks measured on the session's device: register-only loops of
@@ -149,6 +150,23 @@ int jacpcg_autotune(jacpcg_session* s, void* stream, int batch, int M, int K, in
  * TOP/s. A calibration aid: it allocates a small output buffer and
  * synchronises `stream`. Errors: E_INVALID_ARG (NULL), E_HIP. */
 int jacpcg_mfma_peaks(jacpcg_session* s, void* stream, double* tflops);
+
+/* Read or pin one autotuned launch choice. knob names and their values:
+ *   "gram_waves"      waves per Gram workgroup splitting the antennas: 2, 4, 8
+ *                     (split-BF16 Gram: at most 4); key (M, K, Gram precision)
+ *   "precoder_nj"     32-column tiles per precoder wave: 1, 2; key (M, K, split),
+ *                     split = 3 for the default split-BF16 epilogue, 0 with
+ *                     JACPCG_EPILOGUE_FP32
+ *   "precoder_mtiles" antenna blocks per split-BF16 precoder workgroup: 1, 2, 4;
+ *                     key (M, K, 3)
+ *   "pcg_a_source"    where the solver keeps A for K <= 64: 1 registers, 2
+ *                     streamed from L2 like larger K; key (0, K, 0)
+ * value 0 restores the kernel's default rule. Choices change the launch, never
+ * the arithmetic of an entry: every value computes the same result up to the
+ * order of FP32 sums. jacpcg_tune_set drops the session's captured graphs.
+ * Errors: E_INVALID_ARG (NULL, unknown knob, value not a choice of the knob). */
+int jacpcg_tune_set(jacpcg_session* s, const char* knob, int M, int K, int variant, int value);
+int jacpcg_tune_get(jacpcg_session* s, const char* knob, int M, int K, int variant, int* value);
 
 /* ---- the three steps ---------------------------------------------------- */
 

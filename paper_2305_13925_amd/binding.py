@@ -125,6 +125,10 @@ def _declare(lib):
                              C.c_int64, C.c_double, _vp, _vp]
     lib.jacpcg_mfma_peaks.argtypes = [_vp, _vp, C.POINTER(C.c_double)]
     lib.jacpcg_mfma_peaks.restype = C.c_int
+    lib.jacpcg_tune_set.argtypes = [_vp, C.c_char_p, C.c_int, C.c_int, C.c_int, C.c_int]
+    lib.jacpcg_tune_set.restype = C.c_int
+    lib.jacpcg_tune_get.argtypes = [_vp, C.c_char_p, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int)]
+    lib.jacpcg_tune_get.restype = C.c_int
     lib.jacpcg_session_set_graphs.argtypes = [_vp, C.c_int]
     lib.jacpcg_autotune.argtypes = [_vp, _vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]
     lib.jacpcg_submit.argtypes = [_vp, C.POINTER(JacpcgRequest), C.POINTER(C.c_uint64)]
@@ -242,6 +246,16 @@ class Session:
         """jacpcg_autotune: time the launch variants of one shape and keep the fastest."""
         _check(lib().jacpcg_autotune(self.handle, _stream(stream), int(batch), int(M), int(K), int(precision),
                                      int(flags)))
+
+    def tune_set(self, knob, M, K, variant, value):
+        """jacpcg_tune_set: pin one launch choice (value 0: the default rule)."""
+        _check(lib().jacpcg_tune_set(self.handle, knob.encode(), int(M), int(K), int(variant), int(value)))
+
+    def tune_get(self, knob, M, K, variant):
+        """jacpcg_tune_get: the chosen value of one knob (0: not tuned)."""
+        v = C.c_int()
+        _check(lib().jacpcg_tune_get(self.handle, knob.encode(), int(M), int(K), int(variant), C.byref(v)))
+        return v.value
 
     def phase_times(self, reset=False):
         ms = (C.c_double * 5)()

@@ -521,6 +521,28 @@ double jacpcg_session_clock_us(jacpcg_session* s) {
   return std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - s->t0).count();
 }
 
+int jacpcg_tune_set(jacpcg_session* s, const char* knob, int M, int K, int variant, int value) {
+  JP_CHECK(knob != nullptr, "knob is NULL");
+  const int k = Tuner::knob_of(knob);
+  JP_CHECK(k >= 0, "unknown knob '%s'", knob);
+  JP_CHECK(Tuner::valid(k, value), "value %d is not a choice of knob '%s'", value, knob);
+  int rc = check_session(s);
+  if (rc) return rc;
+  s->tuner.set(k, M, K, variant, value);
+  s->graph_clear();  // captured graphs hold the previous choices
+  return JACPCG_OK;
+}
+
+int jacpcg_tune_get(jacpcg_session* s, const char* knob, int M, int K, int variant, int* value) {
+  JP_CHECK(knob != nullptr && value != nullptr, "knob or value is NULL");
+  const int k = Tuner::knob_of(knob);
+  JP_CHECK(k >= 0, "unknown knob '%s'", knob);
+  int rc = check_session(s);
+  if (rc) return rc;
+  *value = s->tuner.get(k, M, K, variant);
+  return JACPCG_OK;
+}
+
 int jacpcg_submit(jacpcg_session* s, const jacpcg_request* r, uint64_t* ticket) {
   JP_CHECK(r != nullptr, "request is NULL");
   JP_CHECK(ticket != nullptr, "ticket is NULL");

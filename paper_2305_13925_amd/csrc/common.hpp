@@ -79,6 +79,8 @@ struct PcgLaunch {
                                             // whose blocks' spans are disjoint are zero and skipped (K > 64)
   const double* col_gate;                   // nullable: batch x nrhs; column j is solved only when
   double gate_tol;                          //   col_gate[j] > gate_tol (or NaN); other columns give x = 0
+  int a_source;                             // where A is kept: 0 default (registers up to K = 64, else
+                                            //   streamed from L2), 1 registers, 2 streamed from L2
 };
 
 struct PrecoderLaunch {

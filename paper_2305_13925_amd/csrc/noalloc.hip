@@ -129,6 +129,7 @@ int run_rzf_noalloc(jacpcg_session* s, hipStream_t st, int batch, int M, int K, 
   p.wg_status = wgs;
   p.gdiag = gdiag;
   p.fpart = fpart;
+  p.a_source = s->tuner.pcg_a_source(K);
   e = launch_pcg(p, st, nullptr);
   if (e != hipSuccess) return set_error(JACPCG_E_HIP, hipGetErrorString(e));
 
@@ -153,6 +154,7 @@ int run_rzf_noalloc(jacpcg_session* s, hipStream_t st, int batch, int M, int K, 
   E.status = status;
   E.split = split_epilogue ? 3 : 0;
   E.nj = s->tuner.precoder_nj(M, K, E.split);
+  E.mtiles = s->tuner.precoder_mtiles(M, K, E.split);
   e = launch_precoder(E, st);
   if (e != hipSuccess) return set_error(JACPCG_E_HIP, hipGetErrorString(e));
   return JACPCG_OK;

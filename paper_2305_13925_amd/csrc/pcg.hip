@@ -505,9 +505,12 @@ hipError_t launch_pcg(const PcgLaunch& p, hipStream_t s, int* wg_count_out) {
   if (wg_count_out) *wg_count_out = grid;
   if (grid == 0) return hipSuccess;
   const int kt = (p.K + 31) / 32;
+  // K <= 64: each wave keeps its rows of A in registers, unless the tuned
+  // choice streams them from L2 like larger K.
+  const bool regs = p.a_source != 2;
   switch (kt) {
-    case 1: return launch_kt<1, true>(p, grid, s);
-    case 2: return launch_kt<2, true>(p, grid, s);
+    case 1: return regs ? launch_kt<1, true>(p, grid, s) : launch_kt<1, false>(p, grid, s);
+    case 2: return regs ? launch_kt<2, true>(p, grid, s) : launch_kt<2, false>(p, grid, s);
     case 3: return launch_kt<3, false>(p, grid, s);
     case 4: return launch_kt<4, false>(p, grid, s);
     case 5: return launch_kt<5, false>(p, grid, s);

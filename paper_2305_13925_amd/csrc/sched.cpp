@@ -421,6 +421,7 @@ int Scheduler::launch(Slot& sl, const std::vector<uint64_t>& members, const std:
   p.wg_status = wgs;
   p.gdiag = gdiag;
   p.fpart = fpart;
+  p.a_source = s_->tuner.pcg_a_source(K);
   if (e == hipSuccess) e = launch_pcg(p, st, nullptr);
 
   PrecoderLaunch E{};
@@ -442,6 +443,7 @@ int Scheduler::launch(Slot& sl, const std::vector<uint64_t>& members, const std:
   E.power = (float)r0.power;
   E.split = (r0.flags & JACPCG_EPILOGUE_FP32) ? 0 : 3;
   E.nj = s_->tuner.precoder_nj(M, K, E.split);
+  E.mtiles = s_->tuner.precoder_mtiles(M, K, E.split);
   E.no_vec = vec_ok ? 0 : 1;
   if (e == hipSuccess) e = launch_precoder(E, st);
   if (e == hipSuccess) e = hipMemcpyAsync(sl.h_status, status, (size_t)G * 4, hipMemcpyDeviceToHost, st);

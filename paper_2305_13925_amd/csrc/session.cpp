@@ -297,6 +297,7 @@ int jacpcg_session::run_rzf(hipStream_t st, int batch, int M, int K, const float
     p.gdiag = refine ? nullptr : gdiag;  // refined path: the power factor comes from FP64 X
     p.fpart = fpart;
     p.tile_span = tspan;
+    p.a_source = tuner.pcg_a_source(K);
     e = run(JACPCG_PHASE_SOLVE, [&] { return launch_pcg(p, q, nullptr); });
     if (e != hipSuccess) return e;
 
@@ -336,6 +337,7 @@ int jacpcg_session::run_rzf(hipStream_t st, int batch, int M, int K, const float
       pc.tile_span = tspan;
       pc.col_gate = scale;
       pc.gate_tol = refine_tol;
+      pc.a_source = p.a_source;
       for (int step = 0;; ++step) {
         rs.step = step;
         e = run(JACPCG_PHASE_RESIDUAL, [&] { return launch_refine_step(rs, q); });
@@ -368,6 +370,7 @@ int jacpcg_session::run_rzf(hipStream_t st, int batch, int M, int K, const float
     E.status = status;
     E.split = split_epilogue ? 3 : 0;
     E.nj = tuner.precoder_nj(M, K, E.split);
+    E.mtiles = tuner.precoder_mtiles(M, K, E.split);
     E.fpart64 = refine ? quad : nullptr;  // ||H X64||^2 from the last FP64 residual
     E.ncb64 = n16;
     E.ref_scale = scale;
@@ -689,7 +692,10 @@ int jacpcg_session::autotune(hipStream_t st, int batch, int M, int K, int precis
   S_HIP(launch_fill_synthetic(H, (size_t)batch * M * K, 12345u, st));
   hipEvent_t e0 = get_event(), e1 = get_event();
   auto time_it = [&](auto&& launch) -> float {
-    (void)launch();  // warm-up (code object load, caches)
+    if (launch() != hipSuccess) {  // warm-up (code object load, caches); a choice the kernel rejects
+      (void)hipGetLastError();
+      return 1e30f;
+    }
     (void)hipEventRecord(e0, st);
     for (int r = 0; r < 3; ++r) (void)launch();
     (void)hipEventRecord(e1, st);
@@ -711,19 +717,26 @@ int jacpcg_session::autotune(hipStream_t st, int batch, int M, int K, int precis
   g.stride_a = (int64_t)KK;
   g.gdiag = gdiag;
   g.precision = precision;
-  int best_w = 0;
-  float best_t = 1e30f;
-  for (int w : {2, 4, 8}) {
-    if (precision != 0 && w > 4) continue;  // split kernels take at most 4 waves
-    g.m_split = w;
-    const float t = time_it([&] { return launch_gram(g, st); });
-    if (t < best_t) {
-      best_t = t;
-      best_w = w;
+  // Each knob in turn: time every valid value on the synthetic batch and keep
+  // the fastest (the earlier knobs already at their chosen values).
+  auto pick = [&](int knob, int Mk, int Kk, int variant, std::initializer_list<int> values, auto&& launch_with) {
+    int best = 0;
+    float best_t = 1e30f;
+    for (int v : values) {
+      const float t = time_it([&] { return launch_with(v); });
+      if (t < best_t) {
+        best_t = t;
+        best = v;
+      }
     }
-  }
-  tuner.set_gram_waves(M, K, precision, best_w);
-  g.m_split = best_w;
+    tuner.set(knob, Mk, Kk, variant, best);
+    return best;
+  };
+  g.m_split = pick(kGramWaves, M, K, precision, {2, 4, 8}, [&](int w) {
+    if (precision != 0 && w > 4) return hipErrorInvalidValue;  // split kernels take at most 4 waves
+    g.m_split = w;
+    return launch_gram(g, st);
+  });
   S_HIP(launch_gram(g, st));
   PcgLaunch p{};
   p.A = A;
@@ -735,9 +748,15 @@ int jacpcg_session::autotune(hipStream_t st, int batch, int M, int K, int precis
   p.batch = batch;
   p.K = K;
   p.nrhs = K;
-  p.max_iter = 4;
+  p.max_iter = 8;
   p.gdiag = gdiag;
   p.fpart = fpart;
+  if (K <= 64) {  // where the solver keeps A: registers or streamed from L2
+    p.a_source = pick(kPcgASource, 0, K, 0, {1, 2}, [&](int v) {
+      p.a_source = v;
+      return launch_pcg(p, st, nullptr);
+    });
+  }
   S_HIP(launch_pcg(p, st, nullptr));
   PrecoderLaunch E{};
   E.H = H;
@@ -757,18 +776,17 @@ int jacpcg_session::autotune(hipStream_t st, int batch, int M, int K, int precis
   E.ncb = ncb;
   E.power = 1.0f;
   E.split = (flags & JACPCG_EPILOGUE_FP32) ? 0 : 3;
-  int best_nj = 0;
-  best_t = 1e30f;
   if (K <= 128 && K > 32) {
-    for (int nj : {1, 2}) {
+    E.nj = pick(kPrecoderNj, M, K, E.split, {1, 2}, [&](int nj) {
       E.nj = nj;
-      const float t = time_it([&] { return launch_precoder(E, st); });
-      if (t < best_t) {
-        best_t = t;
-        best_nj = nj;
-      }
-    }
-    tuner.set_precoder_nj(M, K, E.split, best_nj);
+      return launch_precoder(E, st);
+    });
+  }
+  if (E.split == 3) {  // antenna blocks per split-BF16 workgroup
+    E.mtiles = pick(kPrecoderMtiles, M, K, E.split, {1, 2, 4}, [&](int mt) {
+      E.mtiles = mt;
+      return launch_precoder(E, st);
+    });
   }
   event_pool.push_back(e0);
   event_pool.push_back(e1);

@@ -1,5 +1,5 @@
-// Autotuned launch choices with a flat JSON cache:
-//   {"gram_waves": [[M, K, precision, waves], ...], "precoder_nj": [[M, K, split, nj], ...]}
+// Autotuned launch choices with a flat JSON cache, one list per knob:
+//   {"gram_waves": [[M, K, variant, value], ...], "precoder_nj": [...], ...}
 #include "tuner.hpp"
 
 #include <cstdio>
@@ -8,37 +8,64 @@
 
 namespace jacpcg {
 
-int Tuner::gram_waves(int M, int K, int precision) const {
+namespace {
+const char* const kNames[kNumKnobs] = {"gram_waves", "precoder_nj", "precoder_mtiles", "pcg_a_source"};
+}  // namespace
+
+const char* Tuner::name(int knob) { return (knob >= 0 && knob < kNumKnobs) ? kNames[knob] : ""; }
+
+int Tuner::knob_of(const std::string& n) {
+  for (int k = 0; k < kNumKnobs; ++k)
+    if (n == kNames[k]) return k;
+  return -1;
+}
+
+bool Tuner::valid(int knob, int v) {
+  if (v == 0) return true;
+  switch (knob) {
+    case kGramWaves: return v == 2 || v == 4 || v == 8;
+    case kPrecoderNj: return v == 1 || v == 2;
+    case kPrecoderMtiles: return v == 1 || v == 2 || v == 4;
+    case kPcgASource: return v == 1 || v == 2;
+    default: return false;
+  }
+}
+
+int Tuner::get(int knob, int M, int K, int variant) const {
+  if (knob < 0 || knob >= kNumKnobs) return 0;
   std::lock_guard<std::mutex> lk(mu_);
-  auto it = gram_waves_.find(std::make_tuple(M, K, precision));
-  if (it != gram_waves_.end()) return it->second;
-  (void)K;
-  (void)precision;
+  auto it = m_[knob].find(std::make_tuple(M, K, variant));
+  return it != m_[knob].end() ? it->second : 0;
+}
+
+void Tuner::set(int knob, int M, int K, int variant, int value) {
+  if (knob < 0 || knob >= kNumKnobs) return;
+  std::lock_guard<std::mutex> lk(mu_);
+  if (value == 0)
+    m_[knob].erase(std::make_tuple(M, K, variant));
+  else
+    m_[knob][std::make_tuple(M, K, variant)] = value;
+}
+
+int Tuner::gram_waves(int M, int K, int precision) const {
+  const int v = get(kGramWaves, M, K, precision);
+  if (v) return v;
   // Default: enough waves to split long antenna ranges.
   return M >= 2048 ? 8 : 4;
 }
 
-void Tuner::set_gram_waves(int M, int K, int precision, int waves) {
+size_t Tuner::entries() const {
   std::lock_guard<std::mutex> lk(mu_);
-  gram_waves_[std::make_tuple(M, K, precision)] = waves;
-}
-
-int Tuner::precoder_nj(int M, int K, int split) const {
-  std::lock_guard<std::mutex> lk(mu_);
-  auto it = precoder_nj_.find(std::make_tuple(M, K, split));
-  return it != precoder_nj_.end() ? it->second : 0;
-}
-
-void Tuner::set_precoder_nj(int M, int K, int split, int nj) {
-  std::lock_guard<std::mutex> lk(mu_);
-  precoder_nj_[std::make_tuple(M, K, split)] = nj;
+  size_t n = 0;
+  for (const auto& m : m_) n += m.size();
+  return n;
 }
 
 namespace {
 
 // Parse the list of 4-integer entries that follows "key" in a flat JSON text.
 template <class F>
-void parse_list(const std::string& s, const char* key, F&& put) {
+void parse_list(const std::string& s, const std::string& key, F&& put) {
   const size_t k = s.find(key);
   if (k == std::string::npos) return;
   size_t pos = s.find('[', k);
@@ -66,12 +93,11 @@ bool Tuner::load(const std::string& path) {
   ss << f.rdbuf();
   const std::string s = ss.str();
   std::lock_guard<std::mutex> lk(mu_);
-  parse_list(s, "\"gram_waves\"", [&](const int* v) {
-    if (v[3] >= 1 && v[3] <= 8) gram_waves_[std::make_tuple(v[0], v[1], v[2])] = v[3];
-  });
-  parse_list(s, "\"precoder_nj\"", [&](const int* v) {
-    if (v[3] >= 0 && v[3] <= 2) precoder_nj_[std::make_tuple(v[0], v[1], v[2])] = v[3];
-  });
+  for (int knob = 0; knob < kNumKnobs; ++knob) {
+    parse_list(s, std::string("\"") + kNames[knob] + "\"", [&](const int* v) {
+      if (v[3] != 0 && valid(knob, v[3])) m_[knob][std::make_tuple(v[0], v[1], v[2])] = v[3];
+    });
+  }
   return true;
 }
 
@@ -80,20 +106,17 @@ bool Tuner::save(const std::string& path) const {
   std::ofstream f(path);
   if (!f) return false;
   std::lock_guard<std::mutex> lk(mu_);
-  auto dump = [&](const char* key, const std::map<std::tuple<int, int, int>, int>& m) {
-    f << "\"" << key << "\": [";
+  f << "{";
+  for (int knob = 0; knob < kNumKnobs; ++knob) {
+    f << (knob ? ", " : "") << "\"" << kNames[knob] << "\": [";
     bool first = true;
-    for (auto& kv : m) {
+    for (auto& kv : m_[knob]) {
       f << (first ? "" : ", ") << "[" << std::get<0>(kv.first) << ", " << std::get<1>(kv.first) << ", "
         << std::get<2>(kv.first) << ", " << kv.second << "]";
       first = false;
     }
     f << "]";
-  };
-  f << "{";
-  dump("gram_waves", gram_waves_);
-  f << ", ";
-  dump("precoder_nj", precoder_nj_);
+  }
   f << "}\n";
   return true;
 }

@@ -262,3 +262,15 @@ def test_phase_ranges_and_peak_probe_are_linked():
     assert "roctxRangePushA" in out and "roctxRangePop" in out
     # the matrix-core probe validates its arguments on the host
     assert L.jacpcg_mfma_peaks(NULL, NULL, NULL) == bd.E_INVALID_ARG
+
+
+def test_tune_set_validates_knob_and_value():
+    assert L.jacpcg_tune_set(NULL, b"gram_waves", 1024, 64, 2, 4) == bd.E_INVALID_ARG   # no session
+    assert "session" in _err()
+    assert L.jacpcg_tune_set(NULL, b"no_such_knob", 1024, 64, 2, 4) == bd.E_INVALID_ARG
+    assert "unknown knob" in _err()
+    for knob, bad in ((b"gram_waves", 3), (b"precoder_nj", 3), (b"precoder_mtiles", 3), (b"pcg_a_source", 5)):
+        assert L.jacpcg_tune_set(NULL, knob, 1024, 64, 0, bad) == bd.E_INVALID_ARG
+        assert "not a choice" in _err()
+    v = C.c_int(7)
+    assert L.jacpcg_tune_get(NULL, b"pcg_a_source", 0, 64, 0, C.byref(v)) == bd.E_INVALID_ARG

@@ -128,6 +128,10 @@ def test_autotune_keeps_results_within_bar(torch, tmp_path, M, K, precision, fla
         torch.cuda.synchronize()
     text = cache.read_text()
     assert '"gram_waves"' in text and f"[{M}, {K}, {precision}," in text
+    if K <= 64:
+        assert f"[0, {K}, 0, " in text.split('"pcg_a_source"')[1].split("]]")[0] + "]]"
+    if not flags & bd.EPILOGUE_FP32:
+        assert f"[{M}, {K}, 3, " in text.split('"precoder_mtiles"')[1]
     for b in (0, 5):
         ref = oracle.rzf(Hn[b].T.astype(np.complex128), xi, tol=0.0, max_iter=8)
         got = W[b].cpu().numpy().T
@@ -137,3 +141,38 @@ def test_autotune_keeps_results_within_bar(torch, tmp_path, M, K, precision, fla
         W2 = bd.rzf_precoder(s2, H, xi, max_iter=8, precision=precision, flags=flags)
         torch.cuda.synchronize()
     assert torch.equal(W, W2)
+
+
+@pytest.mark.parametrize("knob,M,K,variant,values,precision,flags", [
+    ("gram_waves", 1024, 64, bd.GRAM_BF16X6, (2, 4), bd.GRAM_BF16X6, 0),
+    ("gram_waves", 2048, 128, bd.GRAM_FP32, (2, 4, 8), bd.GRAM_FP32, 0),
+    ("precoder_nj", 1024, 64, 3, (1, 2), bd.GRAM_BF16X6, 0),
+    ("precoder_nj", 512, 96, 0, (1, 2), bd.GRAM_FP32, bd.EPILOGUE_FP32),
+    ("precoder_mtiles", 1024, 64, 3, (1, 2, 4), bd.GRAM_BF16X6, 0),
+    ("precoder_mtiles", 2048, 128, 3, (1, 2, 4), bd.GRAM_FP32, 0),
+    ("pcg_a_source", 0, 64, 0, (1, 2), bd.GRAM_BF16X6, 0),
+    ("pcg_a_source", 0, 40, 0, (1, 2), bd.GRAM_FP32, 0),
+])
+def test_every_tuned_choice_matches_the_oracle(torch, knob, M, K, variant, values, precision, flags):
+    # Each value of each knob, pinned with jacpcg_tune_set, gives the precoder
+    # within the FP32 bar of the oracle at the same iteration count.
+    rng = np.random.default_rng(M + K + len(knob))
+    Mi = M if M else 512
+    Hn = chan(rng, 4, K, Mi)
+    H = torch.from_numpy(Hn).cuda()
+    xi, T = K / 10.0, 8
+    refs = [oracle.rzf(Hn[b].T.astype(np.complex128), xi, tol=0.0, max_iter=T)["W"] for b in (0, 3)]
+    outs = []
+    with bd.Session(0) as s:
+        for v in values:
+            s.tune_set(knob, M, K, variant, v)
+            assert s.tune_get(knob, M, K, variant) == v
+            W = bd.rzf_precoder(s, H, xi, max_iter=T, precision=precision, flags=flags)
+            torch.cuda.synchronize()
+            outs.append(W.cpu().numpy())
+            for b, ref in zip((0, 3), refs):
+                err = np.linalg.norm(outs[-1][b].T - ref) / np.linalg.norm(ref)
+                print(f"{knob}={v} M={Mi} K={K}: err vs oracle {err:.2e}")
+                assert err <= 1e-5, (knob, v, err)
+    for o in outs[1:]:  # the choices change the launch, not the result beyond FP32 summation order
+        assert np.linalg.norm(o - outs[0]) <= 1e-6 * np.linalg.norm(outs[0])
