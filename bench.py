@@ -456,6 +456,8 @@ def precision_rows(bd, torch, sess, stream, keep, reps=5):
                      f"{wp.vr[0]}-{wp.vr[1]}, xi={xi:g}, FP32 PCG to 1e-6 (<= 64 iterations), FP64 refinement "
                      f"to {REFINE_TOL:g} per column", "before_refinement": {}}
     kept = {"H": Hp.cpu().numpy(), "xi": xi, "X64": {}, "X32": {}}
+    for gp in (bd.GRAM_BF16X3, bd.GRAM_FP32, bd.GRAM_BF16X6):  # the session's launch choices for this shape
+        sess.autotune(64, wp.M, wp.K, gp, 0, stream=stream)
     for name, gp in (("bf16x3_gram", bd.GRAM_BF16X3), ("fp32_gram", bd.GRAM_FP32)):
         bd.rzf_precoder(sess, Hp, xi, tol=1e-6, max_iter=64, precision=gp, W=Wp, X_out=X32, stream=stream)
         torch.cuda.synchronize()
@@ -497,6 +499,7 @@ def stress_rows(bd, torch, sess, stream, keep, reps=3):
                      f"(<= 1024 iterations), FP64 refinement to {REFINE_TOL:g} per column"}
     picks = (0, ws.batch - 1)
     prec = bd.GRAM_FP32 | bd.REFINE_FP64
+    sess.autotune(16, ws.M, ws.K, bd.GRAM_FP32, 0, stream=stream)
     for gain in ("literal", "normalised"):
         H = torch.from_numpy(Hs_np).to("cuda")
         if gain == "normalised":

@@ -98,6 +98,18 @@ def run_serving(session, rate_hz=2000.0, warmup_s=1.0, measure_s=10.0, seed=0, t
         by_k[str(K)] = {"requests": int(lk.size), "p50_ms": round(float(np.percentile(lk, 50)), 4),
                         "p99_ms": round(float(np.percentile(lk, 99)), 4)}
     exec_ms = np.array([(r["t_done_us"] - r["t_admit_us"]) / 1e3 for _, r in meas])
+    # How often a request arrives while another request of its batch key is
+    # running on the device: the only case in which admitting it into the
+    # running batch between solver iterations could help.
+    spans = {}
+    for q, r in zip(reqs, results):
+        spans.setdefault((q["M"], q["K"]), []).append((r["t_admit_us"], r["t_done_us"]))
+    for v in spans.values():
+        v.sort()
+    joinable = 0
+    for q, r in meas:
+        t = r["t_submit_us"]
+        joinable += any(a <= t < d for a, d in spans[(q["M"], q["K"])] if not (a == r["t_admit_us"] and d == r["t_done_us"]))
     return {
         "requests": len(meas),
         "offered_req_per_s": rate_hz,
@@ -112,6 +124,7 @@ def run_serving(session, rate_hz=2000.0, warmup_s=1.0, measure_s=10.0, seed=0, t
         "wall_s": wall,
         "max_iters": int(max(r["max_iters"] for _, r in meas)),
         "mean_max_iters": float(np.mean([r["max_iters"] for _, r in meas])),
+        "arrivals_during_same_key_batch": joinable / len(meas),
         "gain": gain,
     }
 
