@@ -113,8 +113,10 @@ void jacpcg_session_destroy(jacpcg_session* s);
 /* Static description of a status code (never NULL). */
 const char* jacpcg_status_string(int status);
 
-/* Detail of the last failing call on this thread ("" if none). */
-const char* jacpcg_last_error(void);
+/* Detail of the last failing call on the calling thread ("" if none). The
+ * detail is kept per thread: s (nullable) names the session the caller is
+ * asking about, and the text names the failure whichever session it was. */
+const char* jacpcg_last_error(const jacpcg_session* s);
 
 /* ABI version: major * 10000 + minor * 100 + patch. */
 int jacpcg_version(void);

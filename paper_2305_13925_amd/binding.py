@@ -93,6 +93,7 @@ _lib = None
 def _declare(lib):
     lib.jacpcg_version.restype = C.c_int
     lib.jacpcg_last_error.restype = C.c_char_p
+    lib.jacpcg_last_error.argtypes = [_vp]
     lib.jacpcg_status_string.restype = C.c_char_p
     lib.jacpcg_status_string.argtypes = [C.c_int]
     lib.jacpcg_session_create.argtypes = [C.c_int, C.c_size_t, C.c_char_p, C.POINTER(_vp)]
@@ -170,7 +171,7 @@ def status_string(code):
 
 
 def last_error():
-    return lib().jacpcg_last_error().decode()
+    return lib().jacpcg_last_error(None).decode()
 
 
 def _check(rc):

@@ -126,7 +126,7 @@ extern "C" {
 
 int jacpcg_version(void) { return 10000; }
 
-const char* jacpcg_last_error(void) { return g_last_error.c_str(); }
+const char* jacpcg_last_error(const jacpcg_session*) { return g_last_error.c_str(); }
 
 const char* jacpcg_status_string(int status) {
   switch (status) {

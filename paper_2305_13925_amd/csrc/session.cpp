@@ -30,8 +30,13 @@ int hip_error(jacpcg_session* s, hipError_t e, const char* what) {
 int jacpcg_session::reserve(const Workspace& ws) {
   if (ws.bytes <= arena_bytes) return JACPCG_OK;
   if (budget && ws.bytes > budget) return set_error(JACPCG_E_OUT_OF_MEMORY, "workspace exceeds the session budget");
-  // Work already enqueued may still use the old arena; captured graphs refer to it.
-  S_HIP(hipDeviceSynchronize());
+  // Work already enqueued may still use the old arena; captured graphs refer
+  // to it. Every call of the session records order_ev at its end, and a call
+  // on another stream first waits for the previous call's event, so the last
+  // call's event completing means every earlier call's work is done: only
+  // that is waited for, not the whole device (the scheduler's slots and
+  // other streams keep running).
+  if (order_valid) S_HIP(hipEventSynchronize(order_ev));
   graph_clear();
   if (arena) S_HIP(hipFree(arena));
   arena = nullptr;
@@ -117,7 +122,9 @@ hipGraphExec_t jacpcg_session::graph_lookup(uint64_t key) {
 void jacpcg_session::graph_insert(uint64_t key, hipGraphExec_t exec) {
   constexpr size_t kMaxGraphs = 32;
   if (graphs.size() >= kMaxGraphs) {
-    (void)hipDeviceSynchronize();  // the evicted graph may still be executing
+    // The evicted graph may still be executing: its launches belong to
+    // earlier calls, all done once the last call's end event completes.
+    if (order_valid) (void)hipEventSynchronize(order_ev);
     (void)hipGraphExecDestroy(graphs.front().exec);
     graphs.erase(graphs.begin());
   }

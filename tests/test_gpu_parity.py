@@ -238,6 +238,40 @@ def test_rzf_tolerance_mode_and_plain_path_agree(torch, sess):
             assert e <= 1e-3
 
 
+@pytest.mark.parametrize("prec", [bd.GRAM_FP32, bd.GRAM_BF16X6])
+def test_rzf_tolerance_mode_column_replay(torch, sess, prec):
+    # The tolerance-stopped precoder end to end at the FP32 bar: its X equals
+    # the solver's on the same Gram bit for bit (which reports each column's
+    # iteration count), X matches the oracle replaying every column for that
+    # many iterations, and W matches the oracle's precoder of that X.
+    w = workload("batched", gain="normalised")
+    n, tol = 3, 1e-5
+    Hn = channel_batch(w, n=n)
+    H = dev(torch, Hn)
+    for xi in w.xi_values():
+        X = torch.empty((n, w.K, w.K), dtype=torch.complex64, device="cuda")
+        W, st, rc = bd.rzf_precoder(sess, H, xi, tol=tol, max_iter=64, precision=prec, X_out=X, stats=True)
+        assert rc == bd.OK
+        A = bd.jacpcg_gram(sess, H, xi, precision=prec)
+        it = torch.zeros((n, w.K), dtype=torch.int32, device="cuda")
+        Xs = bd.jacpcg_solve(sess, A, None, tol=tol, max_iter=64, iters=it)
+        torch.cuda.synchronize()
+        assert torch.equal(X, Xs)
+        itn, Xn, Wn = it.cpu().numpy(), X.cpu().numpy(), W.cpu().numpy()
+        assert int(itn.max()) == st["max_iters"]
+        for b in range(n):
+            Hb = Hn[b].T.astype(np.complex128)
+            Ab = oracle.gram(Hb, xi)
+            cols = [oracle.jacpcg(Ab, np.eye(w.K)[:, j], tol=0.0, max_iter=int(itn[b, j]))["X"][:, 0]
+                    for j in range(w.K)]
+            Xref = np.stack(cols, axis=1)
+            Wref, _ = oracle.precoder(Hb, Xref)
+            ex, ew = rel(Xn[b].T, Xref), rel(Wn[b].T, Wref)
+            print(f"tol {tol:g} prec={prec} xi={xi:g} b={b}: iters {itn[b].min()}-{itn[b].max()} "
+                  f"err X {ex:.2e} W {ew:.2e}")
+            assert ex <= TOL and ew <= TOL
+
+
 def test_rzf_fixed_plain_equals_batched(torch, sess):
     rng = np.random.default_rng(11)
     H = dev(torch, chan(rng, 4, 70, 300))
