@@ -444,6 +444,142 @@ __global__ __launch_bounds__(256) void gram_bf16_small_kernel(GramLaunch g) {
     }
 }
 
+// Split-BF16 Gram for K > 64 without antenna spans: the 32-user blocks are
+// taken in pairs and there is one workgroup per (instance, pair p <= pair q).
+// A diagonal workgroup (p = q) splits the pair's two blocks and forms their
+// three upper tiles, as the K <= 64 kernel does for its two blocks; an
+// off-diagonal one splits the four blocks of pairs p and q and forms the 2 x 2
+// tiles between them. Every upper tile is formed once, each block's split
+// feeds two or three tiles, and a channel row is read by as many workgroups
+// as there are pairs. Waves take every nw-th 16-antenna step; staged loads run
+// two steps ahead when M is a multiple of 32 nw (EXACT), else one.
+template <int NS, bool EXACT, bool DIAG>
+__device__ __forceinline__ void gram_pair_body(const GramLaunch& g, gptr<const float2> Hb, int b, int p, int q,
+                                               float* red) {
+  constexpr int NB = DIAG ? 2 : 4;     // blocks loaded and split
+  constexpr int NTILE = DIAG ? 3 : 4;  // tiles formed
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int nw = blockDim.x >> 6;
+  const int half = lane >> 5, li = lane & 31;
+  // loaded block n -> block of A
+  auto blk = [&](int n) { return n < 2 ? 2 * p + n : 2 * q + n - 2; };
+  // tile t -> (row, column) among the loaded blocks
+  auto trow = [](int t) { return DIAG ? (t < 2 ? 0 : 1) : (t >> 1); };
+  auto tcol = [](int t) { return DIAG ? (t == 0 ? 0 : 1) : 2 + (t & 1); };
+  bool vu[NB];
+  gptr<const float2> row[NB];
+#pragma unroll
+  for (int n = 0; n < NB; ++n) {
+    const int u = blk(n) * 32 + li;
+    vu[n] = u < g.K;
+    row[n] = Hb + (int64_t)(vu[n] ? u : 0) * g.ldh;
+  }
+  const int mstep = nw * 16;
+  const int m0 = wave * 16;
+  const int m1 = g.M;
+  const bool vec = !g.no_vec && ((uintptr_t)g.H % 16 == 0) && (g.ldh % 2 == 0) && (g.stride_h % 2 == 0);
+
+  floatx16 accR[NTILE], accI[NTILE];
+#pragma unroll
+  for (int t = 0; t < NTILE; ++t) {
+    accR[t] = zero16();
+    accI[t] = zero16();
+  }
+  auto load = [&](int n, int m, float (&re)[8], float (&im)[8]) {
+    const int mm = m + 8 * half;
+    if (EXACT || (vec && vu[n] && mm + 8 <= m1)) {
+      gptr<const float4> ptr = reinterpret_cast<gptr<const float4>>(row[n] + mm);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const float4 t = ld4(ptr + c);
+        re[2 * c] = t.x;
+        im[2 * c] = t.y;
+        re[2 * c + 1] = t.z;
+        im[2 * c + 1] = t.w;
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const float2 t = (vu[n] && mm + e < m1) ? ld2(row[n] + mm + e) : make_float2(0.f, 0.f);
+        re[e] = t.x;
+        im[e] = t.y;
+      }
+    }
+  };
+  auto step = [&](float (&re)[NB][8], float (&im)[NB][8], int m, int ahead) {
+    u32x4 Pr[NB][NS], Pi[NB][NS], An[2][NS];
+#pragma unroll
+    for (int n = 0; n < NB; ++n) {
+      split8<NS>(re[n], Pr[n]);
+      split8<NS>(im[n], Pi[n]);
+    }
+    const int mnext = (m + ahead * mstep < m1) ? m + ahead * mstep : m;
+#pragma unroll
+    for (int n = 0; n < NB; ++n) load(n, mnext, re[n], im[n]);
+    __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the products
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int s2 = 0; s2 < NS; ++s2)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) An[a][s2][e] = neg_bf16x2(Pi[a][s2][e]);
+#pragma unroll
+    for (int t = 0; t < NTILE; ++t) {
+      const int a = trow(t), c = tcol(t);
+      split_mma<NS>(Pr[a], Pr[c], accR[t]);
+      split_mma<NS>(Pi[a], Pi[c], accR[t]);
+      split_mma<NS>(Pr[a], Pi[c], accI[t]);
+      split_mma<NS>(An[a], Pr[c], accI[t]);
+    }
+  };
+  if constexpr (EXACT) {
+    float reA[NB][8], imA[NB][8], reB[NB][8], imB[NB][8];
+#pragma unroll
+    for (int n = 0; n < NB; ++n) {
+      load(n, m0, reA[n], imA[n]);
+      load(n, m0 + mstep, reB[n], imB[n]);
+    }
+    for (int m = m0; m < m1; m += 2 * mstep) {
+      step(reA, imA, m, 2);
+      step(reB, imB, m + mstep, 2);
+    }
+  } else {
+    float re[NB][8], im[NB][8];
+    if (m0 < m1) {
+#pragma unroll
+      for (int n = 0; n < NB; ++n) load(n, m0, re[n], im[n]);
+    }
+    for (int m = m0; m < m1; m += mstep) step(re, im, m, 1);
+  }
+#pragma unroll
+  for (int t = 0; t < NTILE; ++t) {
+    if (t > 0) __syncthreads();  // previous tile's write-out has read the buffer
+    reduce_and_write_tile(g, red, accR[t], accI[t], b, blk(trow(t)), blk(tcol(t)), wave, nw, lane);
+  }
+}
+
+__host__ __device__ inline int pair_groups_per_instance(int nt) {
+  const int np = (nt + 1) / 2;
+  return np * (np + 1) / 2;
+}
+
+template <int NS, bool EXACT>
+__global__ __launch_bounds__(256) void gram_bf16_pair_kernel(GramLaunch g) {
+  const int npp = pair_groups_per_instance((g.K + 31) >> 5);
+  const int np = (((g.K + 31) >> 5) + 1) / 2;
+  const int L = xcd_remap(blockIdx.x, gridDim.x);
+  const int b = L / npp;
+  int p, q;
+  upper_tile(L - b * npp, np, p, q);
+  gptr<const float2> Hb = as_global(g.H_ptrs ? g.H_ptrs[b] : g.H + (int64_t)b * g.stride_h);
+  extern __shared__ float red_dyn[];
+  if (p == q)  // workgroup-uniform
+    gram_pair_body<NS, EXACT, true>(g, Hb, b, p, q, red_dyn);
+  else
+    gram_pair_body<NS, EXACT, false>(g, Hb, b, p, q, red_dyn);
+}
+
 }  // namespace
 
 hipError_t launch_gram(const GramLaunch& g, hipStream_t s) {
@@ -485,6 +621,22 @@ hipError_t launch_gram(const GramLaunch& g, hipStream_t s) {
           pick(gram_bf16_small_kernel<3, 1, true>, gram_bf16_small_kernel<3, 1, false>);
         else
           pick(gram_bf16_small_kernel<3, 2, true>, gram_bf16_small_kernel<3, 2, false>);
+      }
+      return hipGetLastError();
+    }
+    if (!g.tile_span) {
+      const dim3 gridp((unsigned)(pair_groups_per_instance(nt) * g.batch));
+      const bool exact = vec && (g.M % (32 * wb) == 0);
+      if (g.precision == 1) {
+        if (exact)
+          hipLaunchKernelGGL((gram_bf16_pair_kernel<2, true>), gridp, block, lds, s, g);
+        else
+          hipLaunchKernelGGL((gram_bf16_pair_kernel<2, false>), gridp, block, lds, s, g);
+      } else {
+        if (exact)
+          hipLaunchKernelGGL((gram_bf16_pair_kernel<3, true>), gridp, block, lds, s, g);
+        else
+          hipLaunchKernelGGL((gram_bf16_pair_kernel<3, false>), gridp, block, lds, s, g);
       }
       return hipGetLastError();
     }

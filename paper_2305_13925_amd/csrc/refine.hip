@@ -58,9 +58,12 @@ __global__ __launch_bounds__(256) void gram64_kernel(Gram64Launch g) {
   const float2* Hb = g.H + (int64_t)b * g.stride_h;
   const bool vec = ((uintptr_t)g.H % 16 == 0) && (g.ldh % 2 == 0) && (g.stride_h % 2 == 0);
 
-  // [operand: block rows i, block columns j][row][antenna]; a diagonal block
-  // stages one operand and reads it for both.
-  __shared__ float2 Hs[2][kG64Rows][kG64Pad];
+  // A diagonal block stages one operand and reads it for both.
+  // Two buffers: stage s is read from buffer s & 1 while stage s + 1 is
+  // written to the other, so one barrier per stage suffices.
+  // [buffer][operand: block rows i, block columns j][row][antenna]
+  __shared__ float2 Hs[2][2][kG64Rows][kG64Pad];
+  int buf = 0;
 
   // Stage loads: each thread moves 2 x 16 bytes per operand (row = e / 8,
   // antennas 2 (e % 8) and 2 (e % 8) + 1 of the stage).
@@ -103,8 +106,8 @@ __global__ __launch_bounds__(256) void gram64_kernel(Gram64Launch g) {
       for (int u = 0; u < 2; ++u) {
         const int e = threadIdx.x + 256 * u;
         const int row = e >> 3, a2 = 2 * (e & 7);
-        Hs[op][row][a2] = make_float2(st[op][u].x, st[op][u].y);
-        Hs[op][row][a2 + 1] = make_float2(st[op][u].z, st[op][u].w);
+        Hs[buf][op][row][a2] = make_float2(st[op][u].x, st[op][u].y);
+        Hs[buf][op][row][a2 + 1] = make_float2(st[op][u].z, st[op][u].w);
       }
     }
   };
@@ -126,8 +129,8 @@ __global__ __launch_bounds__(256) void gram64_kernel(Gram64Launch g) {
       // k slot q: antenna 2p + slot_m, component comp (Re, Im pairs).
 #pragma unroll
       for (int c = 0; c < NT; ++c) {
-        const float2 a = Hs[0][16 * R[c] + li][2 * p + slot_m];
-        const float2 h = Hs[OPJ][16 * C[c] + li][2 * p + slot_m];
+        const float2 a = Hs[buf][0][16 * R[c] + li][2 * p + slot_m];
+        const float2 h = Hs[buf][OPJ][16 * C[c] + li][2 * p + slot_m];
         const double av = comp ? (double)a.y : (double)a.x;
         const double br = comp ? (double)h.y : (double)h.x;
         const double bim = comp ? -(double)h.x : (double)h.y;
@@ -162,11 +165,13 @@ __global__ __launch_bounds__(256) void gram64_kernel(Gram64Launch g) {
   __syncthreads();
   for (int s2 = 0; s2 < nst; ++s2) {
     if (s2 + 1 < nst) load_stage((s2 + 1) * kG64Ant);
-    stage();
-    __syncthreads();  // every wave is done with this stage
+    stage();  // from buffer s2 & 1
     if (s2 + 1 < nst) {
+      // The other buffer was last read in stage s2 - 1, which every wave
+      // finished before the barrier that ended it.
+      buf ^= 1;
       store_stage();
-      __syncthreads();
+      __syncthreads();  // stage s2 + 1 is in place
     }
   }
 

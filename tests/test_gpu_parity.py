@@ -76,7 +76,7 @@ def test_gram_parity(torch, sess, M, K, batch):
 
 @pytest.mark.parametrize("prec", [bd.GRAM_BF16X6, bd.GRAM_BF16X3])
 @pytest.mark.parametrize("M,K,batch", [(1024, 64, 2), (333, 70, 2), (4100, 96, 1), (64, 256, 1), (7, 5, 3),
-                                       (1000, 130, 1)])
+                                       (1000, 130, 1), (4096, 128, 2), (512, 192, 1), (256, 250, 1)])
 def test_gram_split_bf16_parity(torch, sess, prec, M, K, batch):
     # Split-BF16 Gram: three exact parts / six products is FP32-class; hi+lo
     # with three products carries ~2^-16 relative product error.
