@@ -36,12 +36,18 @@ __device__ __forceinline__ void upper_tile16(int t, int nt, int& ti, int& tj) {
 // One workgroup per (instance, 64 x 64 block of the upper block triangle of A).
 // Wave w owns block rows 16w .. 16w+15 against all 64 block columns (four
 // 16 x 16 tiles, so no reduction across waves); in a diagonal block the tiles
-// wholly below the diagonal are formed and discarded. The channel rows of the block
-// pass through LDS 16 antennas at a time, read from global memory with
-// coalesced 16-byte loads one stage ahead (into registers) of the products.
+// wholly below the diagonal are not formed. The channel rows of the block
+// pass through LDS 16 antennas at a time, widened to FP64 once as they are
+// stored: the row operand as (-Im, Re, Im) triples, the column operand as
+// (Re, Im) pairs, so every MFMA operand is a single LDS read:
+//   Re A_ij += (Re h_i, Im h_i) . (Re h_j, Im h_j)   over the slots comp = 0, 1
+//   Im A_ij += (-Im h_i, Re h_i) . (Re h_j, Im h_j)
+// Global loads are coalesced 16-byte loads one stage ahead (into registers)
+// of the products.
 constexpr int kG64Rows = 64;  // block edge
 constexpr int kG64Ant = 16;   // antennas per stage
-constexpr int kG64Pad = kG64Ant + 1;  // LDS row pitch in complex entries (bank spread)
+constexpr int kG64PitchA = 3 * kG64Ant + 1;  // doubles per row operand row (+1: bank spread)
+constexpr int kG64PitchB = 2 * kG64Ant + 1;  // doubles per column operand row
 
 __global__ __launch_bounds__(256) void gram64_kernel(Gram64Launch g) {
   const int nb = (g.K + kG64Rows - 1) / kG64Rows;
@@ -58,12 +64,10 @@ __global__ __launch_bounds__(256) void gram64_kernel(Gram64Launch g) {
   const float2* Hb = g.H + (int64_t)b * g.stride_h;
   const bool vec = ((uintptr_t)g.H % 16 == 0) && (g.ldh % 2 == 0) && (g.stride_h % 2 == 0);
 
-  // A diagonal block stages one operand and reads it for both.
-  // Two buffers: stage s is read from buffer s & 1 while stage s + 1 is
-  // written to the other, so one barrier per stage suffices.
-  // [buffer][operand: block rows i, block columns j][row][antenna]
-  __shared__ float2 Hs[2][2][kG64Rows][kG64Pad];
-  int buf = 0;
+  // Row operand (block rows i) and column operand (block columns j); a
+  // diagonal block stages only the row operand and reads it for both.
+  __shared__ double HsA[kG64Rows][kG64PitchA];
+  __shared__ double HsB[kG64Rows][kG64PitchB];
 
   // Stage loads: each thread moves 2 x 16 bytes per operand (row = e / 8,
   // antennas 2 (e % 8) and 2 (e % 8) + 1 of the stage).
@@ -100,14 +104,24 @@ __global__ __launch_bounds__(256) void gram64_kernel(Gram64Launch g) {
   };
   auto store_stage = [&]() {
 #pragma unroll
-    for (int op = 0; op < 2; ++op) {
-      if (op == 1 && same) break;
-#pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        const int e = threadIdx.x + 256 * u;
-        const int row = e >> 3, a2 = 2 * (e & 7);
-        Hs[buf][op][row][a2] = make_float2(st[op][u].x, st[op][u].y);
-        Hs[buf][op][row][a2 + 1] = make_float2(st[op][u].z, st[op][u].w);
+    for (int u = 0; u < 2; ++u) {
+      const int e = threadIdx.x + 256 * u;
+      const int row = e >> 3, a2 = 2 * (e & 7);
+      const float4 v = st[0][u];
+      double* d = &HsA[row][3 * a2];
+      d[0] = -(double)v.y;
+      d[1] = (double)v.x;
+      d[2] = (double)v.y;
+      d[3] = -(double)v.w;
+      d[4] = (double)v.z;
+      d[5] = (double)v.w;
+      if (!same) {
+        const float4 c = st[1][u];
+        double* f = &HsB[row][2 * a2];
+        f[0] = (double)c.x;
+        f[1] = (double)c.y;
+        f[2] = (double)c.z;
+        f[3] = (double)c.w;
       }
     }
   };
@@ -118,24 +132,25 @@ __global__ __launch_bounds__(256) void gram64_kernel(Gram64Launch g) {
     accR[c] = zero4d();
     accI[c] = zero4d();
   }
-  // The products of one stage for NT tiles (row tile R[t] of operand block 0,
-  // column tile C[t] of operand block OPJ: 1 off the diagonal, 0 on it). Called with compile-time tile lists, so
-  // every LDS offset is static and every product is unconditional.
+  // The products of one stage for NT tiles (row tile R[t] of the row operand,
+  // column tile C[t] of the column operand, or of the row operand on the
+  // diagonal: OPJ 1 or 0). Called with compile-time tile lists, so every LDS
+  // offset is static and every product is unconditional.
   auto products = [&](auto nt_tag, auto opj_tag, const int (&R)[4], const int (&C)[4]) {
     constexpr int NT = decltype(nt_tag)::value;
     constexpr int OPJ = decltype(opj_tag)::value;
 #pragma unroll 2  // full unrolling hoists every operand: one wave per SIMD
     for (int p = 0; p < kG64Ant / 2; ++p) {
-      // k slot q: antenna 2p + slot_m, component comp (Re, Im pairs).
+      // k slot q: antenna 2p + slot_m, component comp.
+      const int ant = 2 * p + slot_m;
 #pragma unroll
       for (int c = 0; c < NT; ++c) {
-        const float2 a = Hs[buf][0][16 * R[c] + li][2 * p + slot_m];
-        const float2 h = Hs[buf][OPJ][16 * C[c] + li][2 * p + slot_m];
-        const double av = comp ? (double)a.y : (double)a.x;
-        const double br = comp ? (double)h.y : (double)h.x;
-        const double bim = comp ? -(double)h.x : (double)h.y;
-        accR[c] = mfma64(av, br, accR[c]);
-        accI[c] = mfma64(av, bim, accI[c]);
+        const double* ra = &HsA[16 * R[c] + li][3 * ant];
+        const double a_plain = ra[1 + comp];  // (Re, Im)[comp]
+        const double a_rot = ra[comp];        // (-Im, Re)[comp]
+        const double bv = OPJ ? HsB[16 * C[c] + li][2 * ant + comp] : HsA[16 * C[c] + li][3 * ant + 1 + comp];
+        accR[c] = mfma64(a_plain, bv, accR[c]);
+        accI[c] = mfma64(a_rot, bv, accI[c]);
       }
     }
   };
@@ -165,13 +180,11 @@ __global__ __launch_bounds__(256) void gram64_kernel(Gram64Launch g) {
   __syncthreads();
   for (int s2 = 0; s2 < nst; ++s2) {
     if (s2 + 1 < nst) load_stage((s2 + 1) * kG64Ant);
-    stage();  // from buffer s2 & 1
+    stage();
+    __syncthreads();  // every wave is done with this stage
     if (s2 + 1 < nst) {
-      // The other buffer was last read in stage s2 - 1, which every wave
-      // finished before the barrier that ended it.
-      buf ^= 1;
       store_stage();
-      __syncthreads();  // stage s2 + 1 is in place
+      __syncthreads();
     }
   }
 
