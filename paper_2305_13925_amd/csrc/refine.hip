@@ -254,11 +254,13 @@ __global__ __launch_bounds__(256) void refine_step_kernel(RefineStepLaunch r) {
     if (!need) return;
   }
 
+  // X64 of the block's columns; entries K .. KM - 1 stay zero, so the
+  // products of steps past K add nothing.
   __shared__ double2 Xs[16][KM + 1];
-  for (int e = threadIdx.x; e < 16 * K; e += 256) {
-    const int jj = e / K, i = e - jj * K;
+  for (int e = threadIdx.x; e < 16 * KM; e += 256) {
+    const int jj = e / KM, i = e - jj * KM;
     double2 x = make_double2(0.0, 0.0);
-    if (jj < ncol) {
+    if (jj < ncol && i < K) {
       const int64_t o = xo + (int64_t)(j0 + jj) * K + i;
       if (r.step == 0) {
         const float2 v = r.X32[o];
@@ -289,56 +291,64 @@ __global__ __launch_bounds__(256) void refine_step_kernel(RefineStepLaunch r) {
     qr[t] = zero4d();
     qi[t] = zero4d();
   }
-  // A-operand of row tile t at complex step kk: conj(A[kk][rt * 16 + li]).
-  // Loads are unconditional (indices clamped into A) and masked where they are
-  // used, and two register buffers alternate, so each step's loads stay in
-  // flight under the previous step's products.
+  // With a = A[kk][i] (so A[i][kk] = conj(a)) and the B-operand x[comp] of
+  // column j at step kk, the k slots comp = 0, 1 of two products give
+  //   Re (A x)_i = a.x Re x + a.y Im x    (A-operand a[comp])
+  //   Im (A x)_i = -a.y Re x + a.x Im x   (A-operand (-a.y, a.x)[comp])
+  // so each operand is one 8-byte load with no select: the second one reads
+  // component 1 - comp and flips its sign bit in slot 0. Loads are
+  // unconditional (indices clamped into A): rows past K are never written and
+  // steps past K meet zeros of X.
+  gptr<const double> Ad = reinterpret_cast<gptr<const double>>(Ab);
   int ia_c[RT];
-  bool rv[RT];
 #pragma unroll
-  for (int t = 0; t < RT; ++t) {
-    const int ia = (w + 4 * t) * 16 + li;
-    rv[t] = ia < K;
-    ia_c[t] = min(ia, K - 1);
-  }
-  auto load_a = [&](int k0, double2 (&dst)[RT]) {
+  for (int t = 0; t < RT; ++t) ia_c[t] = min((w + 4 * t) * 16 + li, K - 1);
+  const uint32_t sign2 = comp ? 0u : 0x80000000u;
+  auto load_a = [&](int k0, double (&d1)[RT], double (&d2)[RT]) {
     const int kk = min(k0 + slot_k, K - 1);
 #pragma unroll
-    for (int t = 0; t < RT; ++t) dst[t] = ld2d(Ab + (int64_t)kk * K + ia_c[t]);
+    for (int t = 0; t < RT; ++t) {
+      const int64_t o = 2 * ((int64_t)kk * K + ia_c[t]);
+      d1[t] = Ad[o + comp];
+      d2[t] = Ad[o + 1 - comp];
+    }
   };
+  const double* xrow = &Xs[li][0].x + comp;
   // One complex step pair k0: operands from the staged values, then the stage
   // is refilled with step k0 + 2 * kStages (clamped into A, so past the end it
   // reloads a valid row and the join never waits), then the products.
   constexpr int kStages = 4;
-  auto step = [&](double2 (&a)[RT], int k0) {
-    const int kk = k0 + slot_k;
-    const bool kv = kk < K;
-    const double2 x = Xs[li][kv ? kk : 0];
-    const double xr = kv ? (comp ? -x.y : x.x) : 0.0;
-    const double xim = kv ? (comp ? x.x : x.y) : 0.0;
-    double av[RT];
+  auto step = [&](double (&a1)[RT], double (&a2)[RT], int k0) {
+    const double xv = xrow[2 * (k0 + slot_k)];
+    double b2[RT];
 #pragma unroll
-    for (int t = 0; t < RT; ++t) av[t] = (rv[t] && kv) ? (comp ? -a[t].y : a[t].x) : 0.0;
-    load_a(k0 + 2 * kStages, a);
+    for (int t = 0; t < RT; ++t) {
+      const uint64_t u = __builtin_bit_cast(uint64_t, a2[t]) ^ ((uint64_t)sign2 << 32);
+      b2[t] = __builtin_bit_cast(double, u);
+    }
+    double c1[RT];  // the stage is refilled before the products
+#pragma unroll
+    for (int t = 0; t < RT; ++t) c1[t] = a1[t];
+    load_a(k0 + 2 * kStages, a1, a2);
     __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the products
-    // Every row tile is formed (rows beyond K are masked to zero): a branch
+    // Every row tile is formed (rows beyond K give discarded rows): a branch
     // around the products, though wave-uniform, makes the compiler move the
     // accumulators between register files around each one.
 #pragma unroll
     for (int t = 0; t < RT; ++t) {
-      qr[t] = mfma64(av[t], xr, qr[t]);
-      qi[t] = mfma64(av[t], xim, qi[t]);
+      qr[t] = mfma64(c1[t], xv, qr[t]);
+      qi[t] = mfma64(b2[t], xv, qi[t]);
     }
   };
-  double2 st[kStages][RT];
+  double st1[kStages][RT], st2[kStages][RT];
 #pragma unroll
   for (int u = 0; u < kStages; ++u) {
-    load_a(2 * u, st[u]);
+    load_a(2 * u, st1[u], st2[u]);
     __builtin_amdgcn_sched_barrier(0);  // stages issued in order: stage 0 arrives first
   }
   for (int k0 = 0; k0 < K; k0 += 2 * kStages) {
 #pragma unroll
-    for (int u = 0; u < kStages; ++u) step(st[u], k0 + 2 * u);
+    for (int u = 0; u < kStages; ++u) step(st1[u], st2[u], k0 + 2 * u);
   }
 
   // Own rows of the result: rt*16 + q + 4*g, column j0 + li.
