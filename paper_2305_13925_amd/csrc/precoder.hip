@@ -353,6 +353,16 @@ __global__ __launch_bounds__(64 * NW) void precoder_bf16_kernel(PrecoderLaunch e
         compute(hrA, hiA, nth_active(act, i), i + 2);
         if (i + 1 < nact) compute(hrB, hiB, nth_active(act, i + 1), i + 3);
       }
+    } else if constexpr (KT >= 3) {
+      // Fully unrolled over the block's steps: as a loop, the compiler copied
+      // the staged channel values into the loop-carried registers at the back
+      // edge and waited there for every load in flight, including the ones
+      // just issued for the steps ahead.
+#pragma unroll
+      for (int st = 0; st < S; st += 2, gs += 2) {
+        compute(hrA, hiA, st, gs + 2);
+        compute(hrB, hiB, st + 1, gs + 3);
+      }
     } else {
 #pragma unroll 1
       for (int st = 0; st < S; st += 2, gs += 2) {
