@@ -334,6 +334,42 @@ def single_call_latency(bd, torch, sess, reps=200):
             "config": f"1 x (M={w.M}, K={w.K}), 10 dB, tol {w.tol:g} or {w.max_iter} iterations, FP32 Gram"}
 
 
+def two_sessions(bd, torch, H, xi, T, prec, flags, steps=120):
+    """The headline batch with two sessions on two streams of default priority,
+    calls alternating between them with no join in between: consecutive
+    batches overlap (one batch's solve beside the other's Gram or epilogue).
+    Same arguments as the headline; each session replays its own graph."""
+    sessions = [bd.Session(0) for _ in range(2)]
+    streams = [torch.cuda.Stream() for _ in range(2)]
+    Hs = [H, H.clone(), H.clone(), H.clone()]
+    Ws = [torch.empty_like(H) for _ in range(2)]
+    M, K = H.shape[2], H.shape[1]
+    for s in sessions:
+        s.autotune(256, M, K, prec, flags, stream=torch.cuda.current_stream())
+    torch.cuda.synchronize()
+
+    def step(i):
+        j = i % 2
+        bd.rzf_precoder(sessions[j], Hs[2 * ((i // 2) % 2) + j], xi, power=1.0, tol=0.0, max_iter=T, precision=prec,
+                        flags=flags, W=Ws[j], stream=streams[j])
+
+    for i in range(8):
+        step(i)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        step(i)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    for s in sessions:
+        s.close()
+    del Hs, Ws
+    torch.cuda.empty_cache()
+    batch = H.shape[0]
+    return {"ms_per_batch": round(dt * 1e3 / steps, 4), "precoders_per_s": round(steps * batch / dt, 1),
+            "config": "headline batches alternating between two sessions on two streams, no join between calls"}
+
+
 def next_rows(bd, torch, sess, H, xi, stream, samples, reps=20):
     """Throughput of the adjacent rows on the headline channels: per-symbol
     transmission (one symbol vector per instance), the subarray-block
@@ -755,6 +791,8 @@ def main():
         progress("headline variants (SNR, gain)")
         rows["headline_variants"] = headline_variants(bd, torch, sess, H, H_host, stream, samples)
         rows["single_call"] = single_call_latency(bd, torch, sess)
+        progress("two sessions on two streams")
+        rows["two_sessions"] = two_sessions(bd, torch, H, xi, T, prec, flags)
         progress("precision workload (refined)")
         rows["precision"] = precision_rows(bd, torch, sess, stream, keep)
         progress("stress workload (refined, dense and visibility-region sparse)")
