@@ -231,8 +231,8 @@ __global__ __launch_bounds__(256) void gram64_kernel(Gram64Launch g) {
 // so the A-operand entry A[i][k] is read as conj(A[k][i]): the 16 lanes of one
 // k slot then load 256 contiguous bytes of row k. Wave w owns the row tiles
 // w, w + 4, ...; k is outermost, so its row tiles' products are independent
-// accumulation chains, and the next step's A entries are loaded one step
-// ahead of the products.
+// accumulation chains, and the A entries are loaded four steps ahead of the
+// products.
 template <int RT>
 __global__ __launch_bounds__(256) void refine_step_kernel(RefineStepLaunch r) {
   constexpr int KM = 64 * RT;  // largest K of this variant
