@@ -157,3 +157,23 @@ def test_requests_differing_in_one_setting_never_share_a_batch(torch, sess):
         W_dir = bd.rzf_precoder(sess, H, 1.6, tol=1e-6, max_iter=mi)
         torch.cuda.synchronize()
         assert torch.equal(W, W_dir), (M, K, mi)
+
+
+@pytest.mark.parametrize("prec,M,K", [(bd.GRAM_BF16X6, 1024, 64), (bd.GRAM_BF16X6, 1024, 128),
+                                      (bd.GRAM_BF16X3, 512, 96)])
+def test_split_gram_requests_equal_direct_calls(torch, sess, prec, M, K):
+    # Split-BF16 requests of one key (the K <= 64 Gram and the block-pair Gram
+    # above it, channels read through per-instance pointers when batched):
+    # each result equals the direct call on its own channels bit for bit.
+    Ha = device_pool(M, 4, K, 0.6, (2, 4), 3, 31)
+    Hb = device_pool(M, 4, K, 0.6, (2, 4), 5, 32)
+    Wa, Wb = torch.empty_like(Ha), torch.empty_like(Hb)
+    xi = K / 10.0
+    ta = bd.jacpcg_submit(sess, Ha, Wa, xi, tol=0.0, max_iter=8, precision=prec)
+    tb = bd.jacpcg_submit(sess, Hb, Wb, xi, tol=0.0, max_iter=8, precision=prec)
+    for t in (ta, tb):
+        assert bd.jacpcg_wait(sess, t, 20000)["status"] == bd.OK
+    for H, W in ((Ha, Wa), (Hb, Wb)):
+        Wd = bd.rzf_precoder(sess, H, xi, tol=0.0, max_iter=8, precision=prec)
+        torch.cuda.synchronize()
+        assert torch.equal(W, Wd)
