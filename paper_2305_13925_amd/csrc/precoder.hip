@@ -195,12 +195,16 @@ __device__ __forceinline__ int nth_active(unsigned act, int n) {
   return last;
 }
 
+// With one column tile per wave at 64 < K <= 128 the kernel is held to 168
+// registers, three waves per SIMD (170 unconstrained, which allowed two): more
+// waves in flight overlap the channel reads with the products (K = 128,
+// 256 x (M=4096): 0.73 -> 0.66 ms).
 // VR: visibility-region sparse variant (one antenna block per workgroup):
 // only the user steps whose 32-user block has a span reaching this block's
 // antennas are computed (the others hold zero channel entries here).
 // NW waves per workgroup, one 32-antenna tile each: blocks of 32 NW antennas.
 template <int NS, int KT, int NJ, bool FULL, bool VR, int NW>
-__global__ __launch_bounds__(64 * NW) void precoder_bf16_kernel(PrecoderLaunch e) {
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu((KT == 3 || KT == 4) && NJ == 1 ? 3 : 1))) void precoder_bf16_kernel(PrecoderLaunch e) {
   constexpr int BLK = 32 * NW;
   constexpr int KP = KT * 32;
   constexpr int K8 = KP / 8;  // groups of 8 users (one lane half of one step)
@@ -353,11 +357,12 @@ __global__ __launch_bounds__(64 * NW) void precoder_bf16_kernel(PrecoderLaunch e
         compute(hrA, hiA, nth_active(act, i), i + 2);
         if (i + 1 < nact) compute(hrB, hiB, nth_active(act, i + 1), i + 3);
       }
-    } else if constexpr (KT >= 3) {
+    } else if constexpr (KT > 4) {
       // Fully unrolled over the block's steps: as a loop, the compiler copied
       // the staged channel values into the loop-carried registers at the back
       // edge and waited there for every load in flight, including the ones
-      // just issued for the steps ahead.
+      // just issued for the steps ahead. (At K <= 128 the rolled loop fits
+      // three waves per SIMD, which gains more.)
 #pragma unroll
       for (int st = 0; st < S; st += 2, gs += 2) {
         compute(hrA, hiA, st, gs + 2);

@@ -218,6 +218,25 @@ def test_rzf_fixed_iterations(torch, sess, name, gain, n, prec, flags):
             assert abs(np.linalg.norm(Wn[b]) ** 2 - 1.0) <= 1e-5
 
 
+@pytest.mark.parametrize("M,K", [(512, 96), (500, 80), (1024, 128), (384, 100), (256, 72)])
+def test_split_epilogue_across_user_tiles(torch, sess, M, K):
+    # The split-BF16 epilogue for 64 < K <= 128 (three and four 32-user tiles,
+    # whole and ragged antenna blocks and user tiles) against the oracle at
+    # the same iteration count.
+    rng = np.random.default_rng(M * 7 + K)
+    H = chan(rng, 2, K, M)
+    xi, T = K / 10.0, 8
+    W, st, rc = bd.rzf_precoder(sess, dev(torch, H), xi, tol=0.0, max_iter=T, stats=True,
+                                precision=bd.GRAM_BF16X6)
+    assert rc == bd.OK
+    Wn = W.cpu().numpy()
+    for b in range(2):
+        ref = oracle.rzf(H[b].T.astype(np.complex128), xi, tol=0.0, max_iter=st["max_iters"])
+        e = rel(Wn[b].T, ref["W"])
+        print(f"split epilogue M={M} K={K} b={b}: err W {e:.2e}")
+        assert e <= TOL
+
+
 def test_rzf_tolerance_mode_and_plain_path_agree(torch, sess):
     w = workload("batched", gain="normalised")
     H = dev(torch, channel_batch(w, n=3))
