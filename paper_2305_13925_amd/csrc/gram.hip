@@ -217,6 +217,159 @@ __global__ __launch_bounds__(512) void gram_f32_kernel(GramLaunch g) {
   reduce_and_write_tile(g, red_dyn, accR, accI, b, ti, tj, wave, nw, lane);
 }
 
+// FP32 Gram for K > 64 without antenna spans: one workgroup (4 waves) per
+// (instance, 64 x 64 block of the upper block triangle); wave w forms the
+// 32 x 32 tile (w / 2, w % 2) of the block over the whole antenna range (on a
+// diagonal block the tile below the diagonal is formed and not written). The
+// block's channel rows pass through LDS 16 antennas at a time, stored as
+// (-Im, Re, Im) triples (row operand) and (Re, Im) pairs (column operand), so
+// that with the two k slots of v_mfma_f32_32x32x2_f32 carrying one antenna
+//   Re A_ij += (Re h_i, Im h_i).(Re h_j, Im h_j)
+//   Im A_ij += (-Im h_i, Re h_i).(Re h_j, Im h_j)
+// and every operand is one LDS read. Each channel value is loaded once per
+// block from global memory (the tile-per-workgroup kernel above reads each
+// row once per tile it meets, with twice the loads per product).
+constexpr int kG32Ant = 16;
+constexpr int kG32PitchA = 3 * kG32Ant + 1;  // floats per row operand row (+1: bank spread)
+constexpr int kG32PitchB = 2 * kG32Ant + 1;
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void gram_f32_block_kernel(GramLaunch g) {
+  const int nb = (g.K + 63) >> 6;
+  const int nblk = nb * (nb + 1) / 2;
+  const int L = xcd_remap(blockIdx.x, gridDim.x);
+  const int b = L / nblk;
+  int bi, bj;
+  upper_tile(L - b * nblk, nb, bi, bj);
+  const bool same = bi == bj;
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int kk = lane >> 5, li = lane & 31;
+  const int ti = w >> 1, tj = w & 1;
+  gptr<const float2> Hb = as_global(g.H_ptrs ? g.H_ptrs[b] : g.H + (int64_t)b * g.stride_h);
+  const bool vec = !g.no_vec && ((uintptr_t)g.H % 16 == 0) && (g.ldh % 2 == 0) && (g.stride_h % 2 == 0);
+
+  __shared__ float HsA[64][kG32PitchA];
+  __shared__ float HsB[64][kG32PitchB];
+  // Stage loads: each thread moves 2 x 16 bytes per operand (row = e / 8,
+  // antennas 2 (e % 8) and 2 (e % 8) + 1 of the stage).
+  float4 st[2][2];
+  auto load_stage = [&](int m) {
+#pragma unroll
+    for (int op = 0; op < 2; ++op) {
+      if (op == 1 && same) break;  // block-uniform
+      const int blk = op == 0 ? bi : bj;
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int e = threadIdx.x + 256 * u;
+        const int row = e >> 3, a2 = 2 * (e & 7);
+        const int k = blk * 64 + row, mm = m + a2;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (k < g.K) {
+          gptr<const float2> src = Hb + (int64_t)k * g.ldh + mm;
+          if (vec && mm + 2 <= g.M) {
+            v = ld4(reinterpret_cast<gptr<const float4>>(src));
+          } else {
+            if (mm < g.M) {
+              const float2 t = ld2(src);
+              v.x = t.x;
+              v.y = t.y;
+            }
+            if (mm + 1 < g.M) {
+              const float2 t = ld2(src + 1);
+              v.z = t.x;
+              v.w = t.y;
+            }
+          }
+        }
+        st[op][u] = v;
+      }
+    }
+  };
+  auto store_stage = [&]() {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int e = threadIdx.x + 256 * u;
+      const int row = e >> 3, a2 = 2 * (e & 7);
+      const float4 v = st[0][u];
+      float* d = &HsA[row][3 * a2];
+      d[0] = -v.y;
+      d[1] = v.x;
+      d[2] = v.y;
+      d[3] = -v.w;
+      d[4] = v.z;
+      d[5] = v.w;
+      if (!same) {
+        const float4 c = st[1][u];
+        float* f = &HsB[row][2 * a2];
+        f[0] = c.x;
+        f[1] = c.y;
+        f[2] = c.z;
+        f[3] = c.w;
+      }
+    }
+  };
+
+  // Four accumulator pairs take the stage's antennas in turn (p % 4), so each
+  // FP32 chain sums a quarter of the antennas (and four independent chains
+  // keep the matrix core busy); they are added in a fixed order at the end.
+  constexpr int kChains = 4;
+  floatx16 accR[kChains], accI[kChains];
+#pragma unroll
+  for (int c = 0; c < kChains; ++c) {
+    accR[c] = zero16();
+    accI[c] = zero16();
+  }
+  const float* ra = &HsA[32 * ti + li][0];
+  const float* rb = same ? &HsA[32 * tj + li][1] : &HsB[32 * tj + li][0];
+  const int pb = same ? 3 : 2;  // column operand stride per antenna (block-uniform)
+  const int nst = (g.M + kG32Ant - 1) / kG32Ant;
+  load_stage(0);
+  store_stage();
+  __syncthreads();
+  for (int s2 = 0; s2 < nst; ++s2) {
+    if (s2 + 1 < nst) load_stage((s2 + 1) * kG32Ant);
+#pragma unroll
+    for (int p = 0; p < kG32Ant; ++p) {
+      const float a_plain = ra[3 * p + 1 + kk];
+      const float a_rot = ra[3 * p + kk];
+      const float bv = rb[pb * p + kk];
+      accR[p % kChains] = mfma32(a_plain, bv, accR[p % kChains]);
+      accI[p % kChains] = mfma32(a_rot, bv, accI[p % kChains]);
+    }
+    __syncthreads();  // every wave is done with this stage
+    if (s2 + 1 < nst) {
+      store_stage();
+      __syncthreads();
+    }
+  }
+
+  // Write-out from the accumulators: element (i, j) of the tile is register
+  // 4 (i / 8) + i % 4 of lane j + 32 ((i / 4) % 2). Entries above the diagonal
+  // of A are written with their conjugate mirror; a diagonal entry gets xi
+  // and an exactly zero imaginary part; a tile below the diagonal is skipped.
+  const int gti = 2 * bi + ti, gtj = 2 * bj + tj;
+  if (gti > gtj) return;
+  const floatx16 sumR = (accR[0] + accR[1]) + (accR[2] + accR[3]);
+  const floatx16 sumI = (accI[0] + accI[1]) + (accI[2] + accI[3]);
+  float2* Ab = g.A + (int64_t)b * g.stride_a;
+  const int j = li, gj = gtj * 32 + j;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int i = 8 * (r >> 2) + 4 * kk + (r & 3);
+    const int gi = gti * 32 + i;
+    if (gi >= g.K || gj >= g.K || gi > gj) continue;
+    const float re = sumR[r], im = sumI[r];
+    if (gi == gj) {
+      if (g.gdiag) g.gdiag[(int64_t)b * g.K + gi] = re;
+      if (g.diag) g.diag[(int64_t)b * g.K + gi] = re + g.xi;
+      Ab[(int64_t)gi * g.lda + gj] = make_float2(re + g.xi, 0.f);
+    } else {
+      Ab[(int64_t)gi * g.lda + gj] = make_float2(re, im);
+      Ab[(int64_t)gj * g.lda + gi] = make_float2(re, -im);
+    }
+  }
+}
+
 // Split-BF16 Gram: one workgroup per (instance, panel of up to two tiles of one
 // tile row), so the split of the row block's users is shared by both tiles.
 // Real-plane formulation on v_mfma_f32_32x32x16_bf16: the 16 k slots are 16
@@ -591,7 +744,10 @@ hipError_t launch_gram(const GramLaunch& g, hipStream_t s) {
   const dim3 block(64 * waves);
   const bool vec = !g.no_vec && ((uintptr_t)g.H % 16 == 0) && (g.ldh % 2 == 0) && (g.stride_h % 2 == 0);
   const size_t lds = (size_t)waves * 2 * 16 * 64 * sizeof(float);
-  if (g.precision == 0) {
+  if (g.precision == 0 && nt > 2 && !g.tile_span) {
+    const int nb = (g.K + 63) / 64;
+    hipLaunchKernelGGL(gram_f32_block_kernel, dim3((unsigned)(nb * (nb + 1) / 2 * g.batch)), dim3(256), 0, s, g);
+  } else if (g.precision == 0) {
     const dim3 grid((unsigned)(nt * (nt + 1) / 2 * g.batch));
     if (vec)
       hipLaunchKernelGGL(gram_f32_kernel<true>, grid, block, lds, s, g);
