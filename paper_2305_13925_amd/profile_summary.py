@@ -181,6 +181,23 @@ def busy(a):
         rec[phase] = {"kernel": short_name(k[0]), "us": us, "clock_ghz": ghz, "mfma_busy": frac}
         lines.append(f"| {phase} | `{short_name(k[0])[:60]}` | {k[1]} | {len(v)} | {us:.1f} | {ghz:.2f} | "
                      f"{frac:.3f} |")
+    # Every launch group of the library's kernels (kernel, grid), by total time.
+    groups = []
+    for k, v in per.items():
+        name = short_name(k[0])
+        if not any(name.startswith(pf) for pf in PHASE_PREFIX.values()):
+            continue
+        tot = sum(d["us"] for d in v)
+        cyc = sum(d.get("GRBM_GUI_ACTIVE", 0.0) for d in v) / n_xcd
+        mfma = sum(d.get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0) for d in v)
+        groups.append((tot, name, k[1], len(v), cyc, mfma))
+    if groups:
+        lines += ["", "Every launch group of the library's kernels, by total time in the counter pass:\n",
+                  "| kernel | grid | dispatches | avg us | clock GHz | MFMA busy |", "|---|---|---|---|---|---|"]
+        for tot, name, grid, n, cyc, mfma in sorted(groups, reverse=True):
+            ghz = cyc / (tot * 1e3) if tot > 0 else 0.0
+            frac = mfma / (n_simd * cyc) if cyc > 0 else 0.0
+            lines.append(f"| `{name[:60]}` | {grid} | {n} | {tot / n:.1f} | {ghz:.2f} | {frac:.3f} |")
     json.dump(dict(rec, command=a.cmd), open(a.out + ".json", "w"), indent=1)
     open(a.out + ".md", "w").write("\n".join(lines) + "\n")
     print("\n".join(lines))
