@@ -111,6 +111,8 @@ struct Gram64Launch {
   int batch, M, K;
   double xi;
   double2* A64;                             // batch x K x K row-major, ld K
+  const int2* tile_span;                    // nullable: per (instance, 32-user block) antenna spans (as
+                                            // GramLaunch); a block uses only the overlap of its spans
 };
 
 // One refinement step (B = I): X64 += ||r_j|| E_j for the columns that missed

@@ -174,12 +174,37 @@ __global__ __launch_bounds__(256) void gram64_kernel(Gram64Launch g) {
       }
     }
   };
-  const int nst = (g.M + kG64Ant - 1) / kG64Ant;
-  load_stage(0);
+  // Antenna range: all of M, or with visibility-region spans the overlap of
+  // the row block's and the column block's ranges (each the union of its two
+  // 32-user blocks' spans), widened to whole stages (antennas outside a user's
+  // span hold zeros). An empty overlap leaves the block exactly zero.
+  int mb = 0, me = g.M;
+  if (g.tile_span) {
+    const int nt = (g.K + 31) >> 5;
+    auto range64 = [&](int blk, int& lo, int& hi) {
+      lo = g.M;
+      hi = 0;
+      for (int t = 2 * blk; t < min(2 * blk + 2, nt); ++t) {
+        const int2 sp = g.tile_span[(int64_t)b * nt + t];
+        if (sp.y > sp.x) {
+          lo = min(lo, sp.x);
+          hi = max(hi, sp.y);
+        }
+      }
+    };
+    int lo0, hi0, lo1, hi1;
+    range64(bi, lo0, hi0);
+    range64(bj, lo1, hi1);
+    const int lo = max(lo0, lo1), hi = min(hi0, hi1);
+    mb = hi > lo ? (lo / kG64Ant) * kG64Ant : 0;
+    me = hi > lo ? min(g.M, hi) : 0;
+  }
+  const int nst = (me - mb + kG64Ant - 1) / kG64Ant;
+  load_stage(mb);
   store_stage();
   __syncthreads();
   for (int s2 = 0; s2 < nst; ++s2) {
-    if (s2 + 1 < nst) load_stage((s2 + 1) * kG64Ant);
+    if (s2 + 1 < nst) load_stage(mb + (s2 + 1) * kG64Ant);
     stage();
     __syncthreads();  // every wave is done with this stage
     if (s2 + 1 < nst) {

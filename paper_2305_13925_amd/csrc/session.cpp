@@ -253,7 +253,7 @@ int jacpcg_session::run_rzf(hipStream_t st, int batch, int M, int K, const float
       if (e != hipSuccess) return e;
     }
     if (refine) {
-      Gram64Launch g64{H, ldh, stride_h, batch, M, K, xi, A64};
+      Gram64Launch g64{H, ldh, stride_h, batch, M, K, xi, A64, tspan};
       e = run(JACPCG_PHASE_GRAM64, [&] { return launch_gram64(g64, q); });
       if (e != hipSuccess) return e;
     }

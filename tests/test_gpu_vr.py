@@ -107,3 +107,27 @@ def test_vr_stress_full_size_refined_sampled(torch, sess):
         e = rel(W[b].cpu().numpy().T, Ws)
         print(f"  b={b}: W err vs FP64 direct {e:.2e}")
         assert e <= 1e-6
+
+
+def test_vr_refined_x_matches_the_fp64_inverse(torch, sess):
+    # The refined sparse path forms its FP64 Gram over each block's antenna
+    # overlap only. Its X (rounded once from X64 to complex64) against the
+    # FP64 direct inverse and against the refined dense path: a block missing
+    # a nonzero channel entry would leave X off by far more than the rounding.
+    w = small_stress(128)
+    H, spans = sorted_channel_batch(w, n=2)
+    Hd = torch.from_numpy(H).cuda()
+    prec = bd.GRAM_FP32 | bd.REFINE_FP64
+    X_vr = torch.empty((2, w.K, w.K), dtype=torch.complex64, device="cuda")
+    X_dn = torch.empty_like(X_vr)
+    _, st, rc = bd.rzf_precoder_vr(sess, Hd, 1e-2, user_span=torch.from_numpy(spans).cuda(), tol=1e-6,
+                                   max_iter=1024, precision=prec, X_out=X_vr, stats=True)
+    assert rc == bd.OK and st["max_refine_residual"] <= 1e-10, st
+    bd.rzf_precoder(sess, Hd, 1e-2, tol=1e-6, max_iter=1024, precision=prec, X_out=X_dn)
+    torch.cuda.synchronize()
+    for b in range(2):
+        Xs, _, _ = oracle.direct_rzf(H[b].T.astype(np.complex128), 1e-2)
+        e = rel(X_vr[b].cpu().numpy().T.astype(np.complex128), Xs)
+        ed = rel(X_vr[b].cpu().numpy(), X_dn[b].cpu().numpy())
+        print(f"refined vr b={b}: X err vs FP64 inverse {e:.2e}, vs refined dense {ed:.2e}")
+        assert e <= 1e-6 and ed <= 1e-6
