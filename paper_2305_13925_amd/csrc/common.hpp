@@ -132,6 +132,8 @@ struct RefineStepLaunch {
   double* rnorm2;                           // per workgroup: sum_j ||r_j||^2
   double* quad;                             // per workgroup: sum_j Re x_j^H (A64 - xi I) x_j
   int32_t* steps;                           // per workgroup: last step that ran (nullable)
+  const int2* tile_span;                    // nullable: per (instance, 32-user block) antenna spans; rows
+                                            // of A64 meet only the column blocks whose spans overlap theirs
 };
 
 // Visibility-region spans: per user the antenna range [first, end) outside

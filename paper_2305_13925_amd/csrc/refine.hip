@@ -254,10 +254,10 @@ __global__ __launch_bounds__(256) void gram64_kernel(Gram64Launch g) {
 //      sum_j ||H x_j||^2 (FP64, the power factor of the precoder).
 // X64 of the block sits in LDS as the B-operand. A64 is exactly Hermitian,
 // so the A-operand entry A[i][k] is read as conj(A[k][i]): the 16 lanes of one
-// k slot then load 256 contiguous bytes of row k. Wave w owns the row tiles
-// w, w + 4, ...; k is outermost, so its row tiles' products are independent
-// accumulation chains, and the A entries are loaded four steps ahead of the
-// products.
+// k slot then load 256 contiguous bytes of row k. Wave w owns the RT
+// consecutive row tiles from w RT; k is outermost, so its row tiles' products
+// are independent accumulation chains, and the A entries are loaded four
+// steps ahead of the products.
 template <int RT>
 __global__ __launch_bounds__(256) void refine_step_kernel(RefineStepLaunch r) {
   constexpr int KM = 64 * RT;  // largest K of this variant
@@ -327,7 +327,7 @@ __global__ __launch_bounds__(256) void refine_step_kernel(RefineStepLaunch r) {
   gptr<const double> Ad = reinterpret_cast<gptr<const double>>(Ab);
   int ia_c[RT];
 #pragma unroll
-  for (int t = 0; t < RT; ++t) ia_c[t] = min((w + 4 * t) * 16 + li, K - 1);
+  for (int t = 0; t < RT; ++t) ia_c[t] = min((w * RT + t) * 16 + li, K - 1);
   const uint32_t sign2 = comp ? 0u : 0x80000000u;
   auto load_a = [&](int k0, double (&d1)[RT], double (&d2)[RT]) {
     const int kk = min(k0 + slot_k, K - 1);
@@ -365,13 +365,38 @@ __global__ __launch_bounds__(256) void refine_step_kernel(RefineStepLaunch r) {
       qi[t] = mfma64(b2[t], xv, qi[t]);
     }
   };
+  // Range of k the wave's rows meet: all of it, or with visibility-region
+  // spans the wave's own 32-user blocks (xi on the diagonal) and every block
+  // whose span overlaps the hull of theirs (A64[i][k] - xi delta_ik is exactly
+  // zero when users i and k share no antenna), as one range of whole blocks.
+  int klo = 0, khi = K;
+  if (r.tile_span) {
+    const int nt = (K + 31) >> 5;
+    const int2* sp = r.tile_span + (int64_t)b * nt;
+    const int rb0 = min(nt - 1, (w * RT * 16) >> 5);
+    const int rb1 = max(rb0 + 1, min(nt, ((w + 1) * RT * 16 + 31) >> 5));
+    int ulo = 1 << 30, uhi = -1;
+    for (int t = rb0; t < rb1; ++t)
+      if (sp[t].y > sp[t].x) {
+        ulo = min(ulo, sp[t].x);
+        uhi = max(uhi, sp[t].y);
+      }
+    int tlo = rb0, thi = rb1 - 1;
+    for (int t = 0; t < nt; ++t)
+      if (sp[t].y > sp[t].x && sp[t].y > ulo && sp[t].x < uhi) {
+        tlo = min(tlo, t);
+        thi = max(thi, t);
+      }
+    klo = 32 * tlo;
+    khi = min(32 * (thi + 1), KM);
+  }
   double st1[kStages][RT], st2[kStages][RT];
 #pragma unroll
   for (int u = 0; u < kStages; ++u) {
-    load_a(2 * u, st1[u], st2[u]);
+    load_a(klo + 2 * u, st1[u], st2[u]);
     __builtin_amdgcn_sched_barrier(0);  // stages issued in order: stage 0 arrives first
   }
-  for (int k0 = 0; k0 < K; k0 += 2 * kStages) {
+  for (int k0 = klo; k0 < khi; k0 += 2 * kStages) {
 #pragma unroll
     for (int u = 0; u < kStages; ++u) step(st1[u], st2[u], k0 + 2 * u);
   }
@@ -382,7 +407,7 @@ __global__ __launch_bounds__(256) void refine_step_kernel(RefineStepLaunch r) {
   double rre[RT][4], rim[RT][4];
 #pragma unroll
   for (int t = 0; t < RT; ++t) {
-    const int rt = w + 4 * t;
+    const int rt = w * RT + t;
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
       const int i = rt * 16 + q + 4 * g;
@@ -412,7 +437,7 @@ __global__ __launch_bounds__(256) void refine_step_kernel(RefineStepLaunch r) {
   const double inv = sc > 0.0 ? 1.0 / sc : 0.0;
 #pragma unroll
   for (int t = 0; t < RT; ++t) {
-    const int rt = w + 4 * t;
+    const int rt = w * RT + t;
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
       const int i = rt * 16 + q + 4 * g;

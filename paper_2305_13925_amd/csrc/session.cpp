@@ -324,6 +324,7 @@ int jacpcg_session::run_rzf(hipStream_t st, int batch, int M, int K, const float
       rs.rnorm2 = at<double>(oRn);
       rs.quad = quad;
       rs.steps = rsteps;
+      rs.tile_span = tspan;
       PcgLaunch pc{};
       pc.A = A;
       pc.lda = K;
