@@ -301,8 +301,11 @@ int rzf_precoder_plain(jacpcg_session* s, void* stream, int batch, int M, int K,
  * A_ij = 0 when the spans of users i and j do not overlap. Per 32-user block
  * the hull of its users' spans is formed; each Gram tile contracts only the
  * antennas where its two blocks overlap, and the solver skips the tiles of A
- * whose blocks do not overlap (exact zeros). The skipped terms are exact
- * zeros, so the result is rzf_precoder's up to the summation order.
+ * whose blocks do not overlap (exact zeros). With JACPCG_REFINE_FP64 the FP64
+ * Gram contracts each 64 x 64 block over its blocks' overlap too, and the
+ * FP64 residual skips the user blocks a row block does not meet. The skipped
+ * terms are exact zeros, so the result is rzf_precoder's up to the summation
+ * order.
  * Effective for K > 64 (smaller K runs the dense kernels); most effective
  * with users ordered by the position of their region (A then has a band of
  * nonzero tiles).
