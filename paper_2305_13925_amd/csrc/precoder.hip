@@ -180,6 +180,10 @@ hipError_t launch_kt(const PrecoderLaunch& e, hipStream_t s) {
 // beta_pow X is split into bf16 parts once per workgroup (Re and Im planes in
 // LDS); H is split on the fly and its negated Im plane is shared by all column
 // tiles, so no other operand shuffling is needed.
+// Active user steps per chunk of the sparse epilogue's LDS split of beta_pow X
+// (its LDS is sized for this many steps, not for all of K).
+constexpr int kVrSteps = 4;
+
 // Index of the n-th set bit of a step mask (the last set bit when n is past
 // the end, 0 for an empty mask); wave-uniform arguments, scalar work.
 __device__ __forceinline__ int nth_active(unsigned act, int n) {
@@ -209,6 +213,9 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu((KT == 
   constexpr int KP = KT * 32;
   constexpr int K8 = KP / 8;  // groups of 8 users (one lane half of one step)
   constexpr int NC = 32 * NJ;
+  // LDS rows of the split of beta_pow X: every group of 8 users, or for the
+  // sparse variant the active steps of one chunk (kVrSteps steps, 2 rows each).
+  constexpr int K8X = VR ? 2 * kVrSteps : K8;
   const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int jl = lane & 31, half = lane >> 5;
   // A workgroup covers `mt` consecutive blocks of BLK antennas (one 32-antenna
@@ -229,9 +236,9 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu((KT == 
   const int blk0 = mb * mt, blk1 = min(nblk, blk0 + mt);
   const int K = e.K;
 
-  extern __shared__ u32x4 xs_dyn[];  // [2 planes][NS][K8][NC]
+  extern __shared__ u32x4 xs_dyn[];  // [2 planes][NS][K8X][NC]
   auto XS = [&](int plane, int s, int k8, int j) -> u32x4& {
-    return xs_dyn[(((size_t)plane * NS + s) * K8 + k8) * NC + j];
+    return xs_dyn[(((size_t)plane * NS + s) * K8X + k8) * NC + j];
   };
 
   gptr<const float2> Hb = as_global(e.H_ptrs ? e.H_ptrs[b] : e.H + (int64_t)b * e.stride_h);
@@ -290,9 +297,9 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu((KT == 
   }
 
   gptr<const float2> Xb = as_global(e.X + (int64_t)b * e.stride_x);
-  for (int idx = threadIdx.x; idx < K8 * NC; idx += 64 * NW) {
-    const int jj = idx % NC, k8 = idx / NC;
-    if (VR && !((act >> (k8 >> 1)) & 1u)) continue;  // a user step this block never reads
+  // beta_pow X, users 8 k8 .. 8 k8 + 7 of column tile entry jj, split into
+  // LDS row r.
+  auto split_x = [&](int k8, int r, int jj) {
     const int j = cw * NC + jj;
     float re[8], im[8];
 #pragma unroll
@@ -308,18 +315,21 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu((KT == 
     split8<NS>(im, pi);
 #pragma unroll
     for (int q = 0; q < NS; ++q) {
-      XS(0, q, k8, jj) = pr[q];
-      XS(1, q, k8, jj) = pi[q];
+      XS(0, q, r, jj) = pr[q];
+      XS(1, q, r, jj) = pi[q];
     }
+  };
+  if constexpr (!VR) {
+    for (int idx = threadIdx.x; idx < K8 * NC; idx += 64 * NW) split_x(idx / NC, idx / NC, idx % NC);
+    __syncthreads();
   }
-  __syncthreads();
 
   gptr<float2> Wbase = as_global(e.W_ptrs ? e.W_ptrs[b] : e.W + (int64_t)b * e.stride_w);
   floatx16 wr[NJ], wi[NJ];
   // One step: split the staged users, refill the stage with the step two
-  // ahead, then the products of this step's 8 users (per lane half).
-  auto compute = [&](float (&hr)[8], float (&hi)[8], int st, int gs_next) {
-    const int k8 = 2 * st + half;
+  // ahead, then the products of this step's 8 users (per lane half) with the
+  // split of beta_pow X in LDS row k8.
+  auto compute = [&](float (&hr)[8], float (&hi)[8], int k8, int gs_next) {
     u32x4 Hr[NS], Hi[NS], Hn[NS];
     split8<NS>(hr, Hr);
     split8<NS>(hi, Hi);
@@ -352,10 +362,22 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu((KT == 
       wi[t] = zero16();
     }
     if constexpr (VR) {
+      // Active steps in chunks of kVrSteps: the chunk's split of beta_pow X
+      // goes to LDS, then its products.
 #pragma unroll 1
-      for (int i = 0; i < nact; i += 2) {
-        compute(hrA, hiA, nth_active(act, i), i + 2);
-        if (i + 1 < nact) compute(hrB, hiB, nth_active(act, i + 1), i + 3);
+      for (int c0 = 0; c0 < nact; c0 += kVrSteps) {
+        const int c1 = min(nact, c0 + kVrSteps);
+        if (c0 > 0) __syncthreads();  // the previous chunk's products have read the split
+        for (int idx = threadIdx.x; idx < 2 * (c1 - c0) * NC; idx += 64 * NW) {
+          const int r = idx / NC;
+          split_x(2 * nth_active(act, c0 + (r >> 1)) + (r & 1), r, idx % NC);
+        }
+        __syncthreads();
+#pragma unroll 1
+        for (int i = c0; i < c1; i += 2) {
+          compute(hrA, hiA, 2 * (i - c0) + half, i + 2);
+          if (i + 1 < c1) compute(hrB, hiB, 2 * (i + 1 - c0) + half, i + 3);
+        }
       }
     } else if constexpr (KT > 4) {
       // Fully unrolled over the block's steps: as a loop, the compiler copied
@@ -365,14 +387,14 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu((KT == 
       // three waves per SIMD, which gains more.)
 #pragma unroll
       for (int st = 0; st < S; st += 2, gs += 2) {
-        compute(hrA, hiA, st, gs + 2);
-        compute(hrB, hiB, st + 1, gs + 3);
+        compute(hrA, hiA, 2 * st + half, gs + 2);
+        compute(hrB, hiB, 2 * st + 2 + half, gs + 3);
       }
     } else {
 #pragma unroll 1
       for (int st = 0; st < S; st += 2, gs += 2) {
-        compute(hrA, hiA, st, gs + 2);
-        compute(hrB, hiB, st + 1, gs + 3);
+        compute(hrA, hiA, 2 * st + half, gs + 2);
+        compute(hrB, hiB, 2 * st + 2 + half, gs + 3);
       }
     }
     const int m = blk * BLK + w * 32 + jl;
@@ -396,27 +418,30 @@ hipError_t launch_bf16_nj(const PrecoderLaunch& e, hipStream_t s) {
   // leaves room for one workgroup per compute unit, so the workgroup has 8
   // waves (two per SIMD) sharing it, over blocks of 256 antennas.
   constexpr int NW = KT > 4 ? 8 : 4;
-  constexpr int BLK = 32 * NW;
+  // The sparse variant sizes its LDS for kVrSteps active steps, which leaves
+  // room for more than one workgroup per compute unit at any K: 4 waves.
+  constexpr int NWV = 4;
+  const bool vr = e.tile_span != nullptr && KT > 2;
+  const int BLK = 32 * (vr ? NWV : NW);
   const int nblk = (e.M + BLK - 1) / BLK;
   PrecoderLaunch p = e;
   // Blocks of BLK antennas per workgroup: enough to amortise the split of X,
   // few enough to keep several workgroups per compute unit busy. The sparse
   // variant takes one block per workgroup (its user steps depend on it).
-  const bool vr = e.tile_span != nullptr && KT > 2;
   if (vr)
     p.mtiles = 1;
   else if (p.mtiles <= 0)
     p.mtiles = nblk >= 8 ? 2 : 1;
   p.mtiles = std::min(p.mtiles, nblk);
   const int nmb = (nblk + p.mtiles - 1) / p.mtiles;
-  const size_t lds = (size_t)2 * NS * (KT * 4) * 32 * NJ * 16;
+  const size_t lds = (size_t)2 * NS * (vr ? 2 * kVrSteps : KT * 4) * 32 * NJ * 16;
   // FULL: every user, antenna and column of every tile is in range (no masks).
   const bool full = (e.K == KT * 32) && (e.M % BLK == 0) && (e.nrhs % (32 * NJ) == 0);
   const int grid = e.batch * nmb * ((e.nrhs + 32 * NJ - 1) / (32 * NJ));
-  auto k = full ? (vr ? precoder_bf16_kernel<NS, KT, NJ, true, true, NW> : precoder_bf16_kernel<NS, KT, NJ, true, false, NW>)
-                : (vr ? precoder_bf16_kernel<NS, KT, NJ, false, true, NW> : precoder_bf16_kernel<NS, KT, NJ, false, false, NW>);
+  auto k = full ? (vr ? precoder_bf16_kernel<NS, KT, NJ, true, true, NWV> : precoder_bf16_kernel<NS, KT, NJ, true, false, NW>)
+                : (vr ? precoder_bf16_kernel<NS, KT, NJ, false, true, NWV> : precoder_bf16_kernel<NS, KT, NJ, false, false, NW>);
   if (lds > 65536) (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL(k, dim3(grid), dim3(64 * NW), lds, s, p);
+  hipLaunchKernelGGL(k, dim3(grid), dim3(64 * (vr ? NWV : NW)), lds, s, p);
   return hipGetLastError();
 }
 
