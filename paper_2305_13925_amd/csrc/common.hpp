@@ -113,6 +113,8 @@ struct Gram64Launch {
   double2* A64;                             // batch x K x K row-major, ld K
   const int2* tile_span;                    // nullable: per (instance, 32-user block) antenna spans (as
                                             // GramLaunch); a block uses only the overlap of its spans
+  int msplit;                               // >= 2 with partial: the antenna range in msplit chunks
+  double2* partial;                         // batch x blocks x msplit x 64 x 64 partial blocks (nullable)
 };
 
 // One refinement step (B = I): X64 += ||r_j|| E_j for the columns that missed
@@ -165,6 +167,7 @@ size_t pcg_state_floats_per_wg(int K);
 hipError_t launch_status_reduce(const int32_t* wg_status, int ncb, int batch, int32_t* status, hipStream_t s);
 hipError_t launch_precoder(const PrecoderLaunch& e, hipStream_t s);
 hipError_t launch_gram64(const Gram64Launch& g, hipStream_t s);
+int gram64_antenna_chunks(int K, bool spans);  // antenna chunks of the FP64 Gram (1: unsplit)
 hipError_t launch_narrow_gram(const double2* A64, int K, int batch, double xi, float2* A, int64_t lda,
                               int64_t stride_a, float* gdiag, hipStream_t s);
 hipError_t launch_refine_step(const RefineStepLaunch& r, hipStream_t s);

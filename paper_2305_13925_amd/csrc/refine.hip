@@ -53,9 +53,13 @@ __global__ __launch_bounds__(256) void gram64_kernel(Gram64Launch g) {
   const int nb = (g.K + kG64Rows - 1) / kG64Rows;
   const int nblk = nb * (nb + 1) / 2;
   const int L = xcd_remap(blockIdx.x, gridDim.x);
-  const int b = L / nblk;
+  // Split mode: workgroup (instance, block, antenna chunk), chunk innermost.
+  const bool split = g.partial != nullptr && g.msplit > 1;
+  const int S = split ? g.msplit : 1;
+  const int item = L / S, chunk = L - item * S;
+  const int b = item / nblk;
   int bi, bj;
-  upper_tile16(L - b * nblk, nb, bi, bj);
+  upper_tile16(item - b * nblk, nb, bi, bj);
   const bool same = bi == bj;
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -199,6 +203,12 @@ __global__ __launch_bounds__(256) void gram64_kernel(Gram64Launch g) {
     mb = hi > lo ? (lo / kG64Ant) * kG64Ant : 0;
     me = hi > lo ? min(g.M, hi) : 0;
   }
+  if (split) {  // this chunk of the antennas (whole stages)
+    const int cs = ((g.M + S - 1) / S + kG64Ant - 1) / kG64Ant * kG64Ant;
+    mb = max(mb, chunk * cs);
+    me = min(me, (chunk + 1) * cs);
+    if (me <= mb) me = mb;
+  }
   const int nst = (me - mb + kG64Ant - 1) / kG64Ant;
   load_stage(mb);
   store_stage();
@@ -216,9 +226,23 @@ __global__ __launch_bounds__(256) void gram64_kernel(Gram64Launch g) {
   // Element (row q + 4r, column li) of a tile sits in register r. Each entry
   // strictly above the diagonal of A is written with its conjugate mirror, the
   // diagonal gets xi and an exactly zero imaginary part; entries below the
-  // diagonal of a diagonal tile are left to their mirror.
-  double2* Ab = g.A64 + (int64_t)b * g.K * g.K;
+  // diagonal of a diagonal tile are left to their mirror. In split mode the
+  // formed tiles go to this chunk's partial block instead.
   const int wq = min(w, 3);
+  if (split) {
+    double2* Pb = g.partial + (int64_t)L * kG64Rows * kG64Rows;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      if (c >= ntile) continue;
+      const int tr = same ? kDiagR[wq][c] : w;
+      const int tc = same ? kDiagC[wq][c] : c;
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        Pb[(16 * tr + q + 4 * r) * kG64Rows + 16 * tc + li] = make_double2(accR[c][r], accI[c][r]);
+    }
+    return;
+  }
+  double2* Ab = g.A64 + (int64_t)b * g.K * g.K;
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
     if (c >= ntile) continue;
@@ -236,6 +260,38 @@ __global__ __launch_bounds__(256) void gram64_kernel(Gram64Launch g) {
         Ab[(int64_t)gi * g.K + gj] = make_double2(re, im);
         Ab[(int64_t)gj * g.K + gi] = make_double2(re, -im);
       }
+    }
+  }
+}
+
+// Sum of the antenna chunks' partial blocks in chunk order (fixed, so the
+// result does not depend on scheduling), written like gram64_kernel's blocks:
+// entries above the diagonal with their conjugate mirror, xi on the diagonal.
+// One workgroup per (instance, block).
+__global__ __launch_bounds__(256) void gram64_reduce_kernel(Gram64Launch g) {
+  const int nb = (g.K + kG64Rows - 1) / kG64Rows;
+  const int nblk = nb * (nb + 1) / 2;
+  const int item = blockIdx.x;
+  const int b = item / nblk;
+  int bi, bj;
+  upper_tile16(item - b * nblk, nb, bi, bj);
+  const double2* P = g.partial + (int64_t)item * g.msplit * kG64Rows * kG64Rows;
+  double2* Ab = g.A64 + (int64_t)b * g.K * g.K;
+  for (int e = threadIdx.x; e < kG64Rows * kG64Rows; e += 256) {
+    const int i = e / kG64Rows, j = e - i * kG64Rows;
+    const int gi = bi * kG64Rows + i, gj = bj * kG64Rows + j;
+    if (gi >= g.K || gj >= g.K || gi > gj) continue;
+    double re = 0.0, im = 0.0;
+    for (int c = 0; c < g.msplit; ++c) {
+      const double2 v = P[(int64_t)c * kG64Rows * kG64Rows + e];
+      re += v.x;
+      im += v.y;
+    }
+    if (gi == gj) {
+      Ab[(int64_t)gi * g.K + gj] = make_double2(re + g.xi, 0.0);
+    } else {
+      Ab[(int64_t)gi * g.K + gj] = make_double2(re, im);
+      Ab[(int64_t)gj * g.K + gi] = make_double2(re, -im);
     }
   }
 }
@@ -527,8 +583,23 @@ hipError_t launch_fill_synthetic(float2* H, size_t n, uint32_t seed, hipStream_t
 hipError_t launch_gram64(const Gram64Launch& g, hipStream_t s) {
   if (g.batch == 0) return hipSuccess;
   const int nb = (g.K + kG64Rows - 1) / kG64Rows;
-  hipLaunchKernelGGL(gram64_kernel, dim3(nb * (nb + 1) / 2 * g.batch), dim3(256), 0, s, g);
+  const int items = nb * (nb + 1) / 2 * g.batch;
+  if (g.partial && g.msplit > 1) {
+    hipLaunchKernelGGL(gram64_kernel, dim3((unsigned)(items * g.msplit)), dim3(256), 0, s, g);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(gram64_reduce_kernel, dim3((unsigned)items), dim3(256), 0, s, g);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(gram64_kernel, dim3((unsigned)items), dim3(256), 0, s, g);
   return hipGetLastError();
+}
+
+int gram64_antenna_chunks(int K, bool spans) {
+  // Above K = 128 a batch has few 64 x 64 blocks of unequal work (diagonal
+  // blocks form 10 of their 16 tiles) for the compute units; four antenna
+  // chunks per block even out the load. Not with spans (sparse blocks).
+  return (K > 2 * kG64Rows && !spans) ? 4 : 1;
 }
 
 hipError_t launch_narrow_gram(const double2* A64, int K, int batch, double xi, float2* A, int64_t lda,

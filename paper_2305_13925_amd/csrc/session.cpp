@@ -209,6 +209,12 @@ int jacpcg_session::run_rzf(hipStream_t st, int batch, int M, int K, const float
   const int nt = (K + 31) / 32;
   const bool use_spans = vr_sparse && nt > 2;
   const size_t oTS = use_spans ? ws.take<int2>((size_t)batch * nt) : 0;
+  // FP64 Gram in antenna chunks: their partial 64 x 64 blocks
+  const int g64_chunks = refine ? gram64_antenna_chunks(K, use_spans) : 1;
+  const int g64_nb = (K + 63) / 64;
+  const size_t oP64 = g64_chunks > 1
+                          ? ws.take<double2>((size_t)batch * (g64_nb * (g64_nb + 1) / 2) * g64_chunks * 64 * 64)
+                          : 0;
   if (int rc = reserve(ws)) return rc;
   const int2* tspan = use_spans ? at<int2>(oTS) : nullptr;
   float2* A = at<float2>(oA);
@@ -253,7 +259,8 @@ int jacpcg_session::run_rzf(hipStream_t st, int batch, int M, int K, const float
       if (e != hipSuccess) return e;
     }
     if (refine) {
-      Gram64Launch g64{H, ldh, stride_h, batch, M, K, xi, A64, tspan};
+      Gram64Launch g64{H, ldh, stride_h, batch, M, K, xi, A64, tspan, g64_chunks,
+                       g64_chunks > 1 ? at<double2>(oP64) : nullptr};
       e = run(JACPCG_PHASE_GRAM64, [&] { return launch_gram64(g64, q); });
       if (e != hipSuccess) return e;
     }
