@@ -345,7 +345,7 @@ def two_sessions(bd, torch, H, xi, T, prec, flags, steps=120):
     Ws = [torch.empty_like(H) for _ in range(2)]
     M, K = H.shape[2], H.shape[1]
     for s in sessions:
-        s.autotune(256, M, K, prec, flags, stream=torch.cuda.current_stream())
+        s.autotune(H.shape[0], M, K, prec, flags, stream=torch.cuda.current_stream())
     torch.cuda.synchronize()
 
     def step(i):
@@ -493,7 +493,7 @@ def precision_rows(bd, torch, sess, stream, keep, reps=5):
                      f"to {REFINE_TOL:g} per column", "before_refinement": {}}
     kept = {"H": Hp.cpu().numpy(), "xi": xi, "X64": {}, "X32": {}}
     for gp in (bd.GRAM_BF16X3, bd.GRAM_FP32, bd.GRAM_BF16X6):  # the session's launch choices for this shape
-        sess.autotune(64, wp.M, wp.K, gp, 0, stream=stream)
+        sess.autotune(wp.batch, wp.M, wp.K, gp, 0, stream=stream)
     for name, gp in (("bf16x3_gram", bd.GRAM_BF16X3), ("fp32_gram", bd.GRAM_FP32)):
         bd.rzf_precoder(sess, Hp, xi, tol=1e-6, max_iter=64, precision=gp, W=Wp, X_out=X32, stream=stream)
         torch.cuda.synchronize()
@@ -535,7 +535,7 @@ def stress_rows(bd, torch, sess, stream, keep, reps=3):
                      f"(<= 1024 iterations), FP64 refinement to {REFINE_TOL:g} per column"}
     picks = (0, ws.batch - 1)
     prec = bd.GRAM_FP32 | bd.REFINE_FP64
-    sess.autotune(16, ws.M, ws.K, bd.GRAM_FP32, 0, stream=stream)
+    sess.autotune(ws.batch, ws.M, ws.K, bd.GRAM_FP32, 0, stream=stream)
     for gain in ("literal", "normalised"):
         H = torch.from_numpy(Hs_np).to("cuda")
         if gain == "normalised":
@@ -665,7 +665,7 @@ def main():
     # Launch choices for the headline shape from the session's autotuner.
     tuned = None
     if not a.no_tune:
-        sess.autotune(256, M, K, prec, flags, stream=stream)
+        sess.autotune(H.shape[0], M, K, prec, flags, stream=stream)
         split = 0 if flags & bd.EPILOGUE_FP32 else 3
         tuned = {"gram_waves": sess.tune_get("gram_waves", M, K, prec),
                  "pcg_a_source": sess.tune_get("pcg_a_source", 0, K, 0),

@@ -139,8 +139,10 @@ int jacpcg_session_set_graphs(jacpcg_session* s, int enable);
 /* Autotune the launch choices for one shape: times every value of each knob
  * of jacpcg_tune_set that applies (Gram waves; where the solver keeps A for
  * K <= 64; precoder column tiles and antenna blocks) on `batch` synthetic
- * instances of M x K (device memory from the session workspace) and keeps the
- * fastest; the choices are saved to the session's tune cache file at destroy.
+ * instances of M x K (device memory from the session workspace), each value
+ * as the fastest of five launches, and keeps the fastest value. The fastest
+ * choice can differ between batch sizes: pass the batch the calls will use.
+ * The choices are saved to the session's tune cache file at destroy.
  * Synchronises `stream`. Choices depend only on the shape, never on the
  * batch, so results stay independent of batch composition. */
 int jacpcg_autotune(jacpcg_session* s, void* stream, int batch, int M, int K, int precision, int flags);
