@@ -796,17 +796,28 @@ int jacpcg_session::autotune(hipStream_t st, int batch, int M, int K, int precis
   E.ncb = ncb;
   E.power = 1.0f;
   E.split = (flags & JACPCG_EPILOGUE_FP32) ? 0 : 3;
-  if (K <= 128 && K > 32) {
-    E.nj = pick(kPrecoderNj, M, K, E.split, {1, 2}, [&](int nj) {
-      E.nj = nj;
-      return launch_precoder(E, st);
-    });
-  }
-  if (E.split == 3) {  // antenna blocks per split-BF16 workgroup
-    E.mtiles = pick(kPrecoderMtiles, M, K, E.split, {1, 2, 4}, [&](int mt) {
-      E.mtiles = mt;
-      return launch_precoder(E, st);
-    });
+  // Column tiles per wave and (split-BF16) antenna blocks per workgroup
+  // interact, so they are searched together.
+  const bool tune_nj = K <= 128 && K > 32, tune_mt = E.split == 3;
+  if (tune_nj || tune_mt) {
+    int best_nj = 0, best_mt = 0;
+    float best_t = 1e30f;
+    for (int nj : {1, 2}) {
+      if (!tune_nj && nj > 1) break;
+      for (int mt : {1, 2, 4}) {
+        if (!tune_mt && mt > 1) break;
+        E.nj = tune_nj ? nj : 0;
+        E.mtiles = tune_mt ? mt : 0;
+        const float t = time_it([&] { return launch_precoder(E, st); });
+        if (t < best_t) {
+          best_t = t;
+          best_nj = E.nj;
+          best_mt = E.mtiles;
+        }
+      }
+    }
+    if (tune_nj) tuner.set(kPrecoderNj, M, K, E.split, best_nj);
+    if (tune_mt) tuner.set(kPrecoderMtiles, M, K, E.split, best_mt);
   }
   event_pool.push_back(e0);
   event_pool.push_back(e1);
