@@ -48,6 +48,10 @@ def parse():
                     help="measured seconds of the Poisson serving stream (0: skip)")
     ap.add_argument("--no-rows", action="store_true", help="skip the adjacent rows (transmit, block, SINR)")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch choices (no autotuning)")
+    ap.add_argument("--tune-cache", default=None,
+                    help="JSON file of launch choices: shapes found there are not tuned again, new ones are "
+                         "added (counter passes reuse the choices of an unprofiled run: the profiler's "
+                         "serialised dispatches would skew the tuner's timings)")
     ap.add_argument("--rows-only", default=None, choices=["precision", "stress"],
                     help="only run one workload's rows (for per-workload profiles) and print them as JSON")
     ap.add_argument("--calibrate-peaks", action="store_true",
@@ -58,6 +62,19 @@ def parse():
 
 
 PEAK_BF16_MFMA_TFLOPS = 2500.0    # MI355X dense BF16 matrix peak
+TUNE_CACHE = None                 # --tune-cache
+
+
+def session(bd, **kw):
+    return bd.Session(0, tune_cache_path=TUNE_CACHE, **kw)
+
+
+def autotune(sess, batch, M, K, prec, flags, stream):
+    """The session's autotuner for one shape, unless the tune cache already
+    holds that shape's choices."""
+    if TUNE_CACHE and sess.tune_get("gram_waves", M, K, prec):
+        return
+    sess.autotune(batch, M, K, prec, flags, stream=stream)
 
 
 def algorithmic(M, K, n, T, batch, gram, epilogue, T_exec=None):
@@ -339,13 +356,13 @@ def two_sessions(bd, torch, H, xi, T, prec, flags, steps=120):
     calls alternating between them with no join in between: consecutive
     batches overlap (one batch's solve beside the other's Gram or epilogue).
     Same arguments as the headline; each session replays its own graph."""
-    sessions = [bd.Session(0) for _ in range(2)]
+    sessions = [session(bd) for _ in range(2)]
     streams = [torch.cuda.Stream() for _ in range(2)]
     Hs = [H, H.clone(), H.clone(), H.clone()]
     Ws = [torch.empty_like(H) for _ in range(2)]
     M, K = H.shape[2], H.shape[1]
     for s in sessions:
-        s.autotune(H.shape[0], M, K, prec, flags, stream=torch.cuda.current_stream())
+        autotune(s, H.shape[0], M, K, prec, flags, torch.cuda.current_stream())
     torch.cuda.synchronize()
 
     def step(i):
@@ -493,7 +510,7 @@ def precision_rows(bd, torch, sess, stream, keep, reps=5):
                      f"to {REFINE_TOL:g} per column", "before_refinement": {}}
     kept = {"H": Hp.cpu().numpy(), "xi": xi, "X64": {}, "X32": {}}
     for gp in (bd.GRAM_BF16X3, bd.GRAM_FP32, bd.GRAM_BF16X6):  # the session's launch choices for this shape
-        sess.autotune(wp.batch, wp.M, wp.K, gp, 0, stream=stream)
+        autotune(sess, wp.batch, wp.M, wp.K, gp, 0, stream)
     for name, gp in (("bf16x3_gram", bd.GRAM_BF16X3), ("fp32_gram", bd.GRAM_FP32)):
         bd.rzf_precoder(sess, Hp, xi, tol=1e-6, max_iter=64, precision=gp, W=Wp, X_out=X32, stream=stream)
         torch.cuda.synchronize()
@@ -535,7 +552,7 @@ def stress_rows(bd, torch, sess, stream, keep, reps=3):
                      f"(<= 1024 iterations), FP64 refinement to {REFINE_TOL:g} per column"}
     picks = (0, ws.batch - 1)
     prec = bd.GRAM_FP32 | bd.REFINE_FP64
-    sess.autotune(ws.batch, ws.M, ws.K, bd.GRAM_FP32, 0, stream=stream)
+    autotune(sess, ws.batch, ws.M, ws.K, bd.GRAM_FP32, 0, stream)
     for gain in ("literal", "normalised"):
         H = torch.from_numpy(Hs_np).to("cuda")
         if gain == "normalised":
@@ -630,8 +647,10 @@ def main():
     from channelgen import workload, channel_batch
     from paper_2305_13925_amd import binding as bd
 
+    global TUNE_CACHE
+    TUNE_CACHE = a.tune_cache
     if a.rows_only:
-        sess = bd.Session(0)
+        sess = session(bd)
         stream = torch.cuda.current_stream()
         keep = {}
         fn = precision_rows if a.rows_only == "precision" else stress_rows
@@ -652,7 +671,7 @@ def main():
     # 256 MB Infinity Cache (a new channel per step, as in a real stream).
     Hs = (H, H.clone())
     W = torch.empty_like(H)
-    sess = bd.Session(0)
+    sess = session(bd)
     stream = torch.cuda.current_stream()
 
     prec = {"fp32": bd.GRAM_FP32, "bf16x3": bd.GRAM_BF16X3, "bf16x6": bd.GRAM_BF16X6}[a.gram]
@@ -665,7 +684,7 @@ def main():
     # Launch choices for the headline shape from the session's autotuner.
     tuned = None
     if not a.no_tune:
-        sess.autotune(H.shape[0], M, K, prec, flags, stream=stream)
+        autotune(sess, H.shape[0], M, K, prec, flags, stream)
         split = 0 if flags & bd.EPILOGUE_FP32 else 3
         tuned = {"gram_waves": sess.tune_get("gram_waves", M, K, prec),
                  "pcg_a_source": sess.tune_get("pcg_a_source", 0, K, 0),
