@@ -51,6 +51,8 @@ struct GramLaunch {
   int no_vec;       // 1: some channel pointer or ldh does not allow 16-byte loads
   const int2* tile_span;  // nullable: per (instance, 32-user block) antenna span [x, y) outside which
                           // every user of the block has a zero channel; tiles use only the overlap
+  int msplit;             // FP32 Gram above K = 64 with partial: the antenna range in msplit chunks
+  float2* partial;        // batch x blocks x msplit x 64 x 64 partial blocks (nullable)
 };
 
 // Per-workgroup resumable PCG state for chunked launches.
@@ -168,6 +170,7 @@ hipError_t launch_status_reduce(const int32_t* wg_status, int ncb, int batch, in
 hipError_t launch_precoder(const PrecoderLaunch& e, hipStream_t s);
 hipError_t launch_gram64(const Gram64Launch& g, hipStream_t s);
 int gram64_antenna_chunks(int K, bool spans);  // antenna chunks of the FP64 Gram (1: unsplit)
+int gram_antenna_chunks(int K, int precision, bool spans);  // the same for the FP32 Gram
 hipError_t launch_narrow_gram(const double2* A64, int K, int batch, double xi, float2* A, int64_t lda,
                               int64_t stride_a, float* gdiag, hipStream_t s);
 hipError_t launch_refine_step(const RefineStepLaunch& r, hipStream_t s);

@@ -233,13 +233,19 @@ constexpr int kG32Ant = 16;
 constexpr int kG32PitchA = 3 * kG32Ant + 1;  // floats per row operand row (+1: bank spread)
 constexpr int kG32PitchB = 2 * kG32Ant + 1;
 
+// Split mode (partial set, msplit > 1): one workgroup per (instance, block,
+// antenna chunk), chunk innermost; each chunk is a run of whole stages and its
+// tiles go to a partial block that gram_f32_reduce_kernel sums.
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void gram_f32_block_kernel(GramLaunch g) {
   const int nb = (g.K + 63) >> 6;
   const int nblk = nb * (nb + 1) / 2;
   const int L = xcd_remap(blockIdx.x, gridDim.x);
-  const int b = L / nblk;
+  const bool split = g.partial != nullptr && g.msplit > 1;
+  const int S = split ? g.msplit : 1;
+  const int item = L / S, chunk = L - item * S;
+  const int b = item / nblk;
   int bi, bj;
-  upper_tile(L - b * nblk, nb, bi, bj);
+  upper_tile(item - b * nblk, nb, bi, bj);
   const bool same = bi == bj;
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -322,12 +328,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void g
   const float* ra = &HsA[32 * ti + li][0];
   const float* rb = same ? &HsA[32 * tj + li][1] : &HsB[32 * tj + li][0];
   const int pb = same ? 3 : 2;  // column operand stride per antenna (block-uniform)
-  const int nst = (g.M + kG32Ant - 1) / kG32Ant;
-  load_stage(0);
+  // Antenna range: all of M, or this chunk's whole stages.
+  int mb = 0, me = g.M;
+  if (split) {
+    const int cs = ((g.M + S - 1) / S + kG32Ant - 1) / kG32Ant * kG32Ant;
+    mb = min(g.M, chunk * cs);
+    me = min(g.M, mb + cs);
+  }
+  const int nst = (me - mb + kG32Ant - 1) / kG32Ant;
+  load_stage(mb);
   store_stage();
   __syncthreads();
   for (int s2 = 0; s2 < nst; ++s2) {
-    if (s2 + 1 < nst) load_stage((s2 + 1) * kG32Ant);
+    if (s2 + 1 < nst) load_stage(mb + (s2 + 1) * kG32Ant);
 #pragma unroll
     for (int p = 0; p < kG32Ant; ++p) {
       const float a_plain = ra[3 * p + 1 + kk];
@@ -351,6 +364,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void g
   if (gti > gtj) return;
   const floatx16 sumR = (accR[0] + accR[1]) + (accR[2] + accR[3]);
   const floatx16 sumI = (accI[0] + accI[1]) + (accI[2] + accI[3]);
+  if (split) {
+    float2* Pb = g.partial + (int64_t)L * 64 * 64;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int i = 8 * (r >> 2) + 4 * kk + (r & 3);
+      Pb[(32 * ti + i) * 64 + 32 * tj + li] = make_float2(sumR[r], sumI[r]);
+    }
+    return;
+  }
   float2* Ab = g.A + (int64_t)b * g.stride_a;
   const int j = li, gj = gtj * 32 + j;
 #pragma unroll
@@ -359,6 +381,40 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void g
     const int gi = gti * 32 + i;
     if (gi >= g.K || gj >= g.K || gi > gj) continue;
     const float re = sumR[r], im = sumI[r];
+    if (gi == gj) {
+      if (g.gdiag) g.gdiag[(int64_t)b * g.K + gi] = re;
+      if (g.diag) g.diag[(int64_t)b * g.K + gi] = re + g.xi;
+      Ab[(int64_t)gi * g.lda + gj] = make_float2(re + g.xi, 0.f);
+    } else {
+      Ab[(int64_t)gi * g.lda + gj] = make_float2(re, im);
+      Ab[(int64_t)gj * g.lda + gi] = make_float2(re, -im);
+    }
+  }
+}
+
+// Sum of the antenna chunks' partial blocks in chunk order (fixed, so the
+// result does not depend on scheduling), written as gram_f32_block_kernel
+// writes its blocks: mirror above the diagonal, xi on the diagonal, diag and
+// gdiag. One workgroup per (instance, block).
+__global__ __launch_bounds__(256) void gram_f32_reduce_kernel(GramLaunch g) {
+  const int nb = (g.K + 63) >> 6;
+  const int nblk = nb * (nb + 1) / 2;
+  const int item = blockIdx.x;
+  const int b = item / nblk;
+  int bi, bj;
+  upper_tile(item - b * nblk, nb, bi, bj);
+  const float2* P = g.partial + (int64_t)item * g.msplit * 64 * 64;
+  float2* Ab = g.A + (int64_t)b * g.stride_a;
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    const int i = e >> 6, j = e & 63;
+    const int gi = bi * 64 + i, gj = bj * 64 + j;
+    if (gi >= g.K || gj >= g.K || gi > gj) continue;
+    float re = 0.f, im = 0.f;
+    for (int c = 0; c < g.msplit; ++c) {
+      const float2 v = P[(int64_t)c * 64 * 64 + e];
+      re += v.x;
+      im += v.y;
+    }
     if (gi == gj) {
       if (g.gdiag) g.gdiag[(int64_t)b * g.K + gi] = re;
       if (g.diag) g.diag[(int64_t)b * g.K + gi] = re + g.xi;
@@ -746,7 +802,15 @@ hipError_t launch_gram(const GramLaunch& g, hipStream_t s) {
   const size_t lds = (size_t)waves * 2 * 16 * 64 * sizeof(float);
   if (g.precision == 0 && nt > 2 && !g.tile_span) {
     const int nb = (g.K + 63) / 64;
-    hipLaunchKernelGGL(gram_f32_block_kernel, dim3((unsigned)(nb * (nb + 1) / 2 * g.batch)), dim3(256), 0, s, g);
+    const int items = nb * (nb + 1) / 2 * g.batch;
+    if (g.partial && g.msplit > 1) {
+      hipLaunchKernelGGL(gram_f32_block_kernel, dim3((unsigned)(items * g.msplit)), dim3(256), 0, s, g);
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(gram_f32_reduce_kernel, dim3((unsigned)items), dim3(256), 0, s, g);
+    } else {
+      hipLaunchKernelGGL(gram_f32_block_kernel, dim3((unsigned)items), dim3(256), 0, s, g);
+    }
   } else if (g.precision == 0) {
     const dim3 grid((unsigned)(nt * (nt + 1) / 2 * g.batch));
     if (vec)
@@ -810,6 +874,14 @@ hipError_t launch_gram(const GramLaunch& g, hipStream_t s) {
     }
   }
   return hipGetLastError();
+}
+
+int gram_antenna_chunks(int K, int precision, bool spans) {
+  // The FP32 block kernel above K = 128 without spans: 64 instances of
+  // K = 256 give 640 workgroups for 768 slots (2.5 per compute unit), so the
+  // compute units holding three set the time; four antenna chunks per block
+  // give ten equal workgroups per compute unit.
+  return (precision == 0 && K > 128 && !spans) ? 4 : 1;
 }
 
 }  // namespace jacpcg

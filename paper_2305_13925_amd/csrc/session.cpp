@@ -209,12 +209,16 @@ int jacpcg_session::run_rzf(hipStream_t st, int batch, int M, int K, const float
   const int nt = (K + 31) / 32;
   const bool use_spans = vr_sparse && nt > 2;
   const size_t oTS = use_spans ? ws.take<int2>((size_t)batch * nt) : 0;
-  // FP64 Gram in antenna chunks: their partial 64 x 64 blocks
+  // FP64 and FP32 Grams in antenna chunks: their partial 64 x 64 blocks, one
+  // buffer for both (launched one after the other on the same stream)
   const int g64_chunks = refine ? gram64_antenna_chunks(K, use_spans) : 1;
-  const int g64_nb = (K + 63) / 64;
-  const size_t oP64 = g64_chunks > 1
-                          ? ws.take<double2>((size_t)batch * (g64_nb * (g64_nb + 1) / 2) * g64_chunks * 64 * 64)
-                          : 0;
+  const bool fp32_class_gram = !(refine && gram_prec == JACPCG_GRAM_FP64_ROUNDED);
+  const int g32_chunks = fp32_class_gram ? gram_antenna_chunks(K, gram_prec, use_spans) : 1;
+  const int g_nb = (K + 63) / 64;
+  const size_t part_blocks = (size_t)batch * (g_nb * (g_nb + 1) / 2) * 64 * 64;
+  const size_t part_d2 = std::max(g64_chunks > 1 ? part_blocks * g64_chunks : 0,
+                                  g32_chunks > 1 ? (part_blocks * g32_chunks + 1) / 2 : 0);
+  const size_t oPart = part_d2 ? ws.take<double2>(part_d2) : 0;
   if (int rc = reserve(ws)) return rc;
   const int2* tspan = use_spans ? at<int2>(oTS) : nullptr;
   float2* A = at<float2>(oA);
@@ -260,7 +264,7 @@ int jacpcg_session::run_rzf(hipStream_t st, int batch, int M, int K, const float
     }
     if (refine) {
       Gram64Launch g64{H, ldh, stride_h, batch, M, K, xi, A64, tspan, g64_chunks,
-                       g64_chunks > 1 ? at<double2>(oP64) : nullptr};
+                       g64_chunks > 1 ? at<double2>(oPart) : nullptr};
       e = run(JACPCG_PHASE_GRAM64, [&] { return launch_gram64(g64, q); });
       if (e != hipSuccess) return e;
     }
@@ -285,6 +289,8 @@ int jacpcg_session::run_rzf(hipStream_t st, int batch, int M, int K, const float
       g.precision = gram_prec;
       g.m_split = tuner.gram_waves(M, K, gram_prec);
       g.tile_span = tspan;
+      g.msplit = g32_chunks;
+      g.partial = g32_chunks > 1 ? reinterpret_cast<float2*>(at<double2>(oPart)) : nullptr;
       e = run(JACPCG_PHASE_GRAM, [&] { return launch_gram(g, q); });
       if (e != hipSuccess) return e;
     }

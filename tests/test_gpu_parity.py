@@ -338,6 +338,30 @@ def test_rzf_ragged_shapes(torch, sess):
             assert rel(W[b].T, ref["W"]) <= TOL, (M, K, b)
 
 
+@pytest.mark.parametrize("M,K", [(40, 150), (129, 150), (1000, 256), (4100, 200)])
+def test_fp32_gram_antenna_chunks(torch, sess, M, K):
+    # Above K = 128 the precoder's FP32 Gram splits each 64 x 64 block's
+    # antennas into four chunks of whole 16-antenna stages and sums the partial
+    # blocks afterwards; at M = 40 and M = 129 the last chunk is empty, at
+    # M = 4100 the last stage is partial. X (no cancellation in the product
+    # over users) and W against the oracle at the same iteration count.
+    rng = np.random.default_rng(M + 7 * K)
+    H = chan(rng, 2, K, M, spread=3.0)
+    xi, T = K / 10.0, 6
+    X = torch.empty((2, K, K), dtype=torch.complex64, device="cuda")
+    W, st, rc = bd.rzf_precoder(sess, dev(torch, H), xi, tol=0.0, max_iter=T, precision=bd.GRAM_FP32, X_out=X,
+                                stats=True)
+    assert rc == bd.OK, st
+    Xn, Wn = X.cpu().numpy(), W.cpu().numpy()
+    for b in range(2):
+        ref = oracle.rzf(H[b].T.astype(np.complex128), xi, tol=0.0, max_iter=T)
+        ex, ew = rel(Xn[b].T, ref["X"]), rel(Wn[b].T, ref["W"])
+        print(f"fp32 gram chunks M={M} K={K} b={b}: X err {ex:.2e} W err {ew:.2e}")
+        assert ex <= TOL
+        if M >= K:
+            assert ew <= TOL
+
+
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("name,T,samples", [("batched", 8, (0, 1, 513, 1023)), ("precision", 16, (0, 255)),
                                               ("stress", 16, (0, 63))])
