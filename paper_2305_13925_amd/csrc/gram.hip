@@ -395,7 +395,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void g
 // Sum of the antenna chunks' partial blocks in chunk order (fixed, so the
 // result does not depend on scheduling), written as gram_f32_block_kernel
 // writes its blocks: mirror above the diagonal, xi on the diagonal, diag and
-// gdiag. One workgroup per (instance, block).
+// gdiag. One workgroup per (instance, block); the sums pass through LDS so the
+// mirror is written along its rows too.
 __global__ __launch_bounds__(256) void gram_f32_reduce_kernel(GramLaunch g) {
   const int nb = (g.K + 63) >> 6;
   const int nblk = nb * (nb + 1) / 2;
@@ -405,24 +406,34 @@ __global__ __launch_bounds__(256) void gram_f32_reduce_kernel(GramLaunch g) {
   upper_tile(item - b * nblk, nb, bi, bj);
   const float2* P = g.partial + (int64_t)item * g.msplit * 64 * 64;
   float2* Ab = g.A + (int64_t)b * g.stride_a;
+  __shared__ float2 T[64][65];
   for (int e = threadIdx.x; e < 64 * 64; e += 256) {
     const int i = e >> 6, j = e & 63;
     const int gi = bi * 64 + i, gj = bj * 64 + j;
-    if (gi >= g.K || gj >= g.K || gi > gj) continue;
     float re = 0.f, im = 0.f;
     for (int c = 0; c < g.msplit; ++c) {
       const float2 v = P[(int64_t)c * 64 * 64 + e];
       re += v.x;
       im += v.y;
     }
+    T[i][j] = make_float2(re, im);
+    if (gi >= g.K || gj >= g.K || gi > gj) continue;
     if (gi == gj) {
       if (g.gdiag) g.gdiag[(int64_t)b * g.K + gi] = re;
       if (g.diag) g.diag[(int64_t)b * g.K + gi] = re + g.xi;
       Ab[(int64_t)gi * g.lda + gj] = make_float2(re + g.xi, 0.f);
     } else {
       Ab[(int64_t)gi * g.lda + gj] = make_float2(re, im);
-      Ab[(int64_t)gj * g.lda + gi] = make_float2(re, -im);
     }
+  }
+  __syncthreads();
+  // Mirror: row gj of A, columns gi, consecutive threads on consecutive gi.
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    const int j = e >> 6, i = e & 63;
+    const int gi = bi * 64 + i, gj = bj * 64 + j;
+    if (gi >= gj || gj >= g.K) continue;
+    const float2 v = T[i][j];
+    Ab[(int64_t)gj * g.lda + gi] = make_float2(v.x, -v.y);
   }
 }
 

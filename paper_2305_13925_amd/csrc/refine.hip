@@ -267,7 +267,8 @@ __global__ __launch_bounds__(256) void gram64_kernel(Gram64Launch g) {
 // Sum of the antenna chunks' partial blocks in chunk order (fixed, so the
 // result does not depend on scheduling), written like gram64_kernel's blocks:
 // entries above the diagonal with their conjugate mirror, xi on the diagonal.
-// One workgroup per (instance, block).
+// One workgroup per (instance, block); the sums pass through LDS, half a
+// block at a time, so the mirror is written along its rows too.
 __global__ __launch_bounds__(256) void gram64_reduce_kernel(Gram64Launch g) {
   const int nb = (g.K + kG64Rows - 1) / kG64Rows;
   const int nblk = nb * (nb + 1) / 2;
@@ -277,21 +278,33 @@ __global__ __launch_bounds__(256) void gram64_reduce_kernel(Gram64Launch g) {
   upper_tile16(item - b * nblk, nb, bi, bj);
   const double2* P = g.partial + (int64_t)item * g.msplit * kG64Rows * kG64Rows;
   double2* Ab = g.A64 + (int64_t)b * g.K * g.K;
-  for (int e = threadIdx.x; e < kG64Rows * kG64Rows; e += 256) {
-    const int i = e / kG64Rows, j = e - i * kG64Rows;
-    const int gi = bi * kG64Rows + i, gj = bj * kG64Rows + j;
-    if (gi >= g.K || gj >= g.K || gi > gj) continue;
-    double re = 0.0, im = 0.0;
-    for (int c = 0; c < g.msplit; ++c) {
-      const double2 v = P[(int64_t)c * kG64Rows * kG64Rows + e];
-      re += v.x;
-      im += v.y;
+  constexpr int kHalf = kG64Rows / 2;
+  __shared__ double2 T[kHalf][kG64Rows + 1];
+  for (int h = 0; h < 2; ++h) {
+    if (h > 0) __syncthreads();  // the first half's mirror has read T
+    for (int e = threadIdx.x; e < kHalf * kG64Rows; e += 256) {
+      const int il = e / kG64Rows, j = e - il * kG64Rows;
+      const int i = h * kHalf + il;
+      const int gi = bi * kG64Rows + i, gj = bj * kG64Rows + j;
+      double re = 0.0, im = 0.0;
+      for (int c = 0; c < g.msplit; ++c) {
+        const double2 v = P[(int64_t)c * kG64Rows * kG64Rows + i * kG64Rows + j];
+        re += v.x;
+        im += v.y;
+      }
+      T[il][j] = make_double2(re, im);
+      if (gi >= g.K || gj >= g.K || gi > gj) continue;
+      Ab[(int64_t)gi * g.K + gj] = gi == gj ? make_double2(re + g.xi, 0.0) : make_double2(re, im);
     }
-    if (gi == gj) {
-      Ab[(int64_t)gi * g.K + gj] = make_double2(re + g.xi, 0.0);
-    } else {
-      Ab[(int64_t)gi * g.K + gj] = make_double2(re, im);
-      Ab[(int64_t)gj * g.K + gi] = make_double2(re, -im);
+    __syncthreads();
+    // Mirror of this half: rows gj of A, columns gi (consecutive threads on
+    // consecutive gi).
+    for (int e = threadIdx.x; e < kHalf * kG64Rows; e += 256) {
+      const int j = e / kHalf, il = e - j * kHalf;
+      const int gi = bi * kG64Rows + h * kHalf + il, gj = bj * kG64Rows + j;
+      if (gi >= gj || gj >= g.K) continue;
+      const double2 v = T[il][j];
+      Ab[(int64_t)gj * g.K + gi] = make_double2(v.x, -v.y);
     }
   }
 }
