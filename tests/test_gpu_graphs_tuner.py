@@ -176,3 +176,37 @@ def test_every_tuned_choice_matches_the_oracle(torch, knob, M, K, variant, value
                 assert err <= 1e-5, (knob, v, err)
     for o in outs[1:]:  # the choices change the launch, not the result beyond FP32 summation order
         assert np.linalg.norm(o - outs[0]) <= 1e-6 * np.linalg.norm(outs[0])
+
+
+def test_headline_full_size_in_the_benchmark_configuration(torch):
+    # The timed configuration of the benchmark: the full batch of 1024
+    # instances of M = 1024, K = 64 at 10 dB, T = 8, three-part split-BF16 Gram
+    # and epilogue, launch choices autotuned at that batch, repeated calls
+    # replayed from the captured graph. Sampled instances against the oracle
+    # at the same T, the power constraint on every instance, and the replay
+    # equal to the first call bit for bit.
+    from channelgen import channel_batch, workload
+    w = workload("batched")
+    Hn = channel_batch(w)
+    M, K, T = w.M, w.K, w.max_iter
+    xi = K / 10.0
+    H = torch.from_numpy(Hn).cuda()
+    with bd.Session(0) as s:
+        s.autotune(Hn.shape[0], M, K, bd.GRAM_BF16X6, 0)
+        choices = {k: s.tune_get(k, *key) for k, key in (("gram_waves", (M, K, bd.GRAM_BF16X6)),
+                                                          ("pcg_a_source", (0, K, 0)),
+                                                          ("precoder_nj", (M, K, 3)),
+                                                          ("precoder_mtiles", (M, K, 3)))}
+        print(f"tuned choices {choices}")
+        W1 = bd.rzf_precoder(s, H, xi, power=1.0, tol=0.0, max_iter=T, precision=bd.GRAM_BF16X6)
+        W2 = bd.rzf_precoder(s, H, xi, power=1.0, tol=0.0, max_iter=T, precision=bd.GRAM_BF16X6)
+        torch.cuda.synchronize()
+    assert torch.equal(W1, W2)
+    Wn = W1.cpu().numpy()
+    p = np.sum(np.abs(Wn.astype(np.complex128)) ** 2, axis=(1, 2))
+    assert np.max(np.abs(p - 1.0)) <= 1e-5
+    for b in (0, 1, 511, 1023):
+        ref = oracle.rzf(Hn[b].T.astype(np.complex128), xi, tol=0.0, max_iter=T)["W"]
+        err = np.linalg.norm(Wn[b].T - ref) / np.linalg.norm(ref)
+        print(f"headline b={b}: err vs oracle {err:.2e}")
+        assert err <= 1e-5
