@@ -241,6 +241,10 @@ typedef struct {
  *   at most 16 corrections. The power factor comes from ||H X64||_F^2 in FP64
  *   and W from X64 rounded to FP32. An instance with a column still above
  *   refine_tol after 16 corrections reports NOT_CONVERGED.
+ * Above K = 128 (without visibility-region spans) the FP32 Gram and the FP64
+ *   Gram of this call sum the antennas in four chunks, added in a fixed order
+ *   (session workspace: 4 partial 64 x 64 blocks per block of A); the FP32 A
+ *   can then differ from jacpcg_gram's in the last bits.
  * X_out (nullable): column-major K x K c64 copy of X per instance (ld K,
  *   stride K*K). X64_out (nullable): the same in c128 (the refined X64; the
  *   FP32 solution widened otherwise). flags: as jacpcg_solve.
