@@ -163,11 +163,17 @@ int jacpcg_mfma_peaks(jacpcg_session* s, void* stream, double* tflops);
  *                     JACPCG_EPILOGUE_FP32
  *   "precoder_mtiles" antenna blocks per split-BF16 precoder workgroup: 1, 2, 4;
  *                     key (M, K, 3)
- *   "pcg_a_source"    where the solver keeps A for K <= 64: 1 registers, 2
- *                     streamed from L2 like larger K; key (0, K, 0)
- * value 0 restores the kernel's default rule. Choices change the launch, never
- * the arithmetic of an entry: every value computes the same result up to the
- * order of FP32 sums. jacpcg_tune_set drops the session's captured graphs.
+ *   "pcg_a_source"    where the solver keeps A and how it forms A P: 1 in
+ *                     registers (K <= 64), 2 streamed from L2 with FP32
+ *                     products, 3 streamed with split-BF16 products (three
+ *                     bf16 parts of A and P, six part products: FP32-class,
+ *                     the dropped part products at most ~2^-24 of the terms;
+ *                     K > 64 without visibility-region spans, else as the
+ *                     default); key (0, K, 0). Default: 1 up to K = 64, 3 above.
+ * value 0 restores the kernel's default rule. Choices change the launch and
+ * the order of the FP32 sums; the solver's products are FP32 or FP32-class
+ * split-BF16 (pcg_a_source 3) and every choice stays within the FP32 bar of
+ * the others. jacpcg_tune_set drops the session's captured graphs.
  * Errors: E_INVALID_ARG (NULL, unknown knob, value not a choice of the knob). */
 int jacpcg_tune_set(jacpcg_session* s, const char* knob, int M, int K, int variant, int value);
 int jacpcg_tune_get(jacpcg_session* s, const char* knob, int M, int K, int variant, int* value);

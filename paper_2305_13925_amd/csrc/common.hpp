@@ -81,8 +81,11 @@ struct PcgLaunch {
                                             // whose blocks' spans are disjoint are zero and skipped (K > 64)
   const double* col_gate;                   // nullable: batch x nrhs; column j is solved only when
   double gate_tol;                          //   col_gate[j] > gate_tol (or NaN); other columns give x = 0
-  int a_source;                             // where A is kept: 0 default (registers up to K = 64, else
-                                            //   streamed from L2), 1 registers, 2 streamed from L2
+  int a_source;                             // where A is kept and how its products are formed: 0 default
+                                            //   (registers up to K = 64; above, streamed from L2 with split-
+                                            //   BF16 products, FP32 products with spans), 1 registers
+                                            //   (K <= 64), 2 streamed from L2 with FP32 products, 3 streamed
+                                            //   with split-BF16 products (K > 64 without spans; else as 0)
 };
 
 struct PrecoderLaunch {

@@ -126,11 +126,115 @@ __device__ __forceinline__ void apply_a_vr(floatx16& qr, floatx16& qi, const flo
   }
 }
 
+// Split-BF16 variant of the product (K > 64, dense, A streamed from L2): the
+// direction block lives in LDS as three-part bf16 planes PB[comp][part][k8][j]
+// (entry: the 8 bf16 of rows 8 k8 .. 8 k8 + 7 of column j, the B operand of
+// v_mfma_f32_32x32x16_bf16), and each lane splits the 8 entries of its row of A
+// that one 16-row step needs (k = 16 s + 8 half ..), so
+//   Re Q += Re A Re P + (-Im A) Im P,   Im Q += Re A Im P + Im A Re P
+// take four split products of six bf16 MFMAs each (FP32-class: the dropped
+// part products are at most ~2^-24 of the terms).
+template <int NS>
+__device__ __forceinline__ void split4(const float (&x)[4], uint32_t (&parts)[NS][2]) {
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    float a = x[2 * q], b = x[2 * q + 1];
+#pragma unroll
+    for (int t = 0; t < NS; ++t) {
+      const uint32_t pk = pack_bf16x2(a, b);
+      parts[t][q] = pk;
+      if (t + 1 < NS) {
+        a -= bf16_lo(pk);
+        b -= bf16_hi(pk);
+      }
+    }
+  }
+}
+
+// Store this wave's rows of a block (result layout) as the bf16 planes.
+template <int KT>
+__device__ __forceinline__ void store_planes(const float (&vr)[16], const float (&vi)[16], u32x4* PB, int w,
+                                             int half, int jl) {
+  constexpr int K8 = KT * 4;
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    const float xr4[4] = {vr[4 * g], vr[4 * g + 1], vr[4 * g + 2], vr[4 * g + 3]};
+    const float xi4[4] = {vi[4 * g], vi[4 * g + 1], vi[4 * g + 2], vi[4 * g + 3]};
+    uint32_t pr[3][2], pi[3][2];
+    split4<3>(xr4, pr);
+    split4<3>(xi4, pi);
+    const int k8 = 4 * w + g;  // rows 8 k8 + 4 half .. + 3 of the plane entry
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      uint2* er = reinterpret_cast<uint2*>(&PB[((0 * 3 + t) * K8 + k8) * 32 + jl]);
+      uint2* ei = reinterpret_cast<uint2*>(&PB[((1 * 3 + t) * K8 + k8) * 32 + jl]);
+      er[half] = make_uint2(pr[t][0], pr[t][1]);
+      ei[half] = make_uint2(pi[t][0], pi[t][1]);
+    }
+  }
+}
+
+template <int KT>
+__device__ __forceinline__ void apply_a_spl(floatx16& qr, floatx16& qi, const float2* __restrict__ arow, bool rowvalid,
+                                            int K, int ia, bool zero_diag, const u32x4* PB, int half, int jl) {
+  constexpr int K8 = KT * 4;
+  constexpr int NSTEP = KT * 2;  // 16 rows of P per step
+  qr = zero16();
+  qi = zero16();
+  float2 av[2][8];
+  auto load = [&](int st, float2 (&v)[8]) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int k = 16 * st + 8 * half + e;
+      v[e] = (rowvalid && k < K && !(zero_diag && k == ia)) ? arow[k] : make_float2(0.f, 0.f);
+    }
+  };
+  load(0, av[0]);
+#pragma unroll
+  for (int st = 0; st < NSTEP; ++st) {
+    float2(&cur)[8] = av[st & 1];
+    if (st + 1 < NSTEP) load(st + 1, av[(st + 1) & 1]);
+    // Re A's products first, then Im A's, so that few operands are live at
+    // once (the solver state takes most of the registers).
+    u32x4 Pr[3], Pi[3];
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      Pr[t] = PB[((0 * 3 + t) * K8 + 2 * st + half) * 32 + jl];
+      Pi[t] = PB[((1 * 3 + t) * K8 + 2 * st + half) * 32 + jl];
+    }
+    {
+      float re[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) re[e] = cur[e].x;
+      u32x4 Ar[3];
+      split8<3>(re, Ar);
+      split_mma<3>(Ar, Pr, qr);
+      split_mma<3>(Ar, Pi, qi);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    {
+      float im[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) im[e] = cur[e].y;
+      u32x4 Ai[3];
+      split8<3>(im, Ai);
+      split_mma<3>(Ai, Pr, qi);
+#pragma unroll
+      for (int t = 0; t < 3; ++t)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) Ai[t][c] = neg_bf16x2(Ai[t][c]);
+      split_mma<3>(Ai, Pi, qr);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
 // Two waves per SIMD (the register budget of 256 per lane) let one workgroup's
 // reductions overlap another's products.
-template <int KT, bool AREG, bool VRS>
+template <int KT, bool AREG, bool VRS, bool SPL = false>
 __global__ __launch_bounds__(KT * 64) __attribute__((amdgpu_waves_per_eu(2))) void pcg_f32_kernel(PcgLaunch p) {
   static_assert(!(VRS && AREG), "the sparse variant streams A");
+  static_assert(!SPL || (!AREG && !VRS), "the split-BF16 product is for dense streamed A");
   constexpr int KP = KT * 32;
   constexpr int KH = KT * 16;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -145,12 +249,13 @@ __global__ __launch_bounds__(KT * 64) __attribute__((amdgpu_waves_per_eu(2))) vo
   // The direction block P, and before it (K <= 64) the staging tile of A.
   // The direction block P; before it (K <= 64) the staging tile of 32 rows of
   // A, after it the staging tile of X (32 columns of KP + 1 entries).
-  constexpr int kLdsP = KP * 32 * (int)sizeof(float2);
+  constexpr int kLdsP = SPL ? 6 * (KP / 8) * 32 * 16 : KP * 32 * (int)sizeof(float2);
   constexpr int kLdsA = AREG ? 32 * KP * (int)sizeof(float2) : 0;
   constexpr int kLdsX = 32 * (KP + 1) * (int)sizeof(float2);
   constexpr int kLds = kLdsA > kLdsX ? kLdsA : (kLdsX > kLdsP ? kLdsX : kLdsP);
   __shared__ __attribute__((aligned(16))) unsigned char lds_raw[kLds];
   float2(*Psh)[32] = reinterpret_cast<float2(*)[32]>(lds_raw);
+  u32x4* PB = reinterpret_cast<u32x4*>(lds_raw);  // SPL: the bf16 planes of P
   __shared__ float red[3][KT][32];
 
   const bool chunked = p.st.vec != nullptr;
@@ -301,8 +406,12 @@ __global__ __launch_bounds__(KT * 64) __attribute__((amdgpu_waves_per_eu(2))) vo
     t0 = (int)stc[7 * 32 + 0];
   }
 
+  if constexpr (SPL) {
+    store_planes<KT>(pr, pim, PB, w, half, jl);
+  } else {
 #pragma unroll
-  for (int r = 0; r < 16; ++r) Psh[w * 32 + d32_row(r, half)][jl] = make_float2(pr[r], pim[r]);
+    for (int r = 0; r < 16; ++r) Psh[w * 32 + d32_row(r, half)][jl] = make_float2(pr[r], pim[r]);
+  }
 
   // FP32 range guard: below ||r|| = 2^-40 ||b|| an FP32 iterate no longer
   // changes (the update is far under its rounding) while p^H A p heads for
@@ -317,6 +426,8 @@ __global__ __launch_bounds__(KT * 64) __attribute__((amdgpu_waves_per_eu(2))) vo
     floatx16 qr, qi;
     if constexpr (VRS)
       apply_a_vr<KT>(qr, qi, arow_full, ia < K, K, ia, false, vr_mask, Psh, half, jl);
+    else if constexpr (SPL)
+      apply_a_spl<KT>(qr, qi, arow_full, ia < K, K, ia, false, PB, half, jl);
     else
       apply_a<KT, AREG>(qr, qi, ar, ai, arow, klim, false, diag_s, Psh, half, jl);
 
@@ -371,8 +482,12 @@ __global__ __launch_bounds__(KT * 64) __attribute__((amdgpu_waves_per_eu(2))) vo
         pim[r] = dinv[r] * ri[r] + beta * pim[r];
       }
     }
+    if constexpr (SPL) {
+      store_planes<KT>(pr, pim, PB, w, half, jl);
+    } else {
 #pragma unroll
-    for (int r = 0; r < 16; ++r) Psh[w * 32 + d32_row(r, half)][jl] = make_float2(pr[r], pim[r]);
+      for (int r = 0; r < 16; ++r) Psh[w * 32 + d32_row(r, half)][jl] = make_float2(pr[r], pim[r]);
+    }
   }
 
   const bool finished = !__any(active) || t >= p.max_iter;
@@ -436,12 +551,18 @@ __global__ __launch_bounds__(KT * 64) __attribute__((amdgpu_waves_per_eu(2))) vo
   if (p.gdiag) {
     // ||H X||^2 contribution of this block: x_j^H (A - diag(A) + diag(H^H H)) x_j.
     __syncthreads();
+    if constexpr (SPL) {
+      store_planes<KT>(xr, xim, PB, w, half, jl);
+    } else {
 #pragma unroll
-    for (int r = 0; r < 16; ++r) Psh[w * 32 + d32_row(r, half)][jl] = make_float2(xr[r], xim[r]);
+      for (int r = 0; r < 16; ++r) Psh[w * 32 + d32_row(r, half)][jl] = make_float2(xr[r], xim[r]);
+    }
     __syncthreads();
     floatx16 yr, yi;
     if constexpr (VRS)
       apply_a_vr<KT>(yr, yi, arow_full, ia < K, K, ia, true, vr_mask, Psh, half, jl);
+    else if constexpr (SPL)
+      apply_a_spl<KT>(yr, yi, arow_full, ia < K, K, ia, true, PB, half, jl);
     else
       apply_a<KT, AREG>(yr, yi, ar, ai, arow, klim, true, diag_s, Psh, half, jl);
     float q[1] = {0.f};
@@ -483,6 +604,12 @@ hipError_t launch_kt(const PcgLaunch& p, int grid, hipStream_t s) {
       hipLaunchKernelGGL((pcg_f32_kernel<KT, false, true>), dim3(grid), dim3(KT * 64), 0, s, p);
       return hipGetLastError();
     }
+    if constexpr (KT >= 3) {
+      if (p.a_source != 2) {  // split-BF16 products (the default above K = 64)
+        hipLaunchKernelGGL((pcg_f32_kernel<KT, false, false, true>), dim3(grid), dim3(KT * 64), 0, s, p);
+        return hipGetLastError();
+      }
+    }
   }
   hipLaunchKernelGGL((pcg_f32_kernel<KT, AREG, false>), dim3(grid), dim3(KT * 64), 0, s, p);
   return hipGetLastError();
@@ -506,7 +633,9 @@ hipError_t launch_pcg(const PcgLaunch& p, hipStream_t s, int* wg_count_out) {
   if (grid == 0) return hipSuccess;
   const int kt = (p.K + 31) / 32;
   // K <= 64: each wave keeps its rows of A in registers, unless the tuned
-  // choice streams them from L2 like larger K.
+  // choice streams them from L2 (FP32 products). Above K = 64 the rows are
+  // streamed with split-BF16 products, unless the choice is FP32 products or
+  // the spans of the sparse variant apply.
   const bool regs = p.a_source != 2;
   switch (kt) {
     case 1: return regs ? launch_kt<1, true>(p, grid, s) : launch_kt<1, false>(p, grid, s);

@@ -777,11 +777,16 @@ int jacpcg_session::autotune(hipStream_t st, int batch, int M, int K, int precis
   p.max_iter = 8;
   p.gdiag = gdiag;
   p.fpart = fpart;
-  if (K <= 64) {  // where the solver keeps A: registers or streamed from L2
-    p.a_source = pick(kPcgASource, 0, K, 0, {1, 2}, [&](int v) {
+  {  // where the solver keeps A (registers or streamed from L2) and, above
+     // K = 64, FP32 or split-BF16 products
+    auto solve_with = [&](int v) {
       p.a_source = v;
       return launch_pcg(p, st, nullptr);
-    });
+    };
+    if (K <= 64)
+      p.a_source = pick(kPcgASource, 0, K, 0, {1, 2}, solve_with);
+    else
+      p.a_source = pick(kPcgASource, 0, K, 0, {2, 3}, solve_with);
   }
   S_HIP(launch_pcg(p, st, nullptr));
   PrecoderLaunch E{};

@@ -26,7 +26,7 @@ bool Tuner::valid(int knob, int v) {
     case kGramWaves: return v == 2 || v == 4 || v == 8;
     case kPrecoderNj: return v == 1 || v == 2;
     case kPrecoderMtiles: return v == 1 || v == 2 || v == 4;
-    case kPcgASource: return v == 1 || v == 2;
+    case kPcgASource: return v >= 1 && v <= 3;
     default: return false;
   }
 }

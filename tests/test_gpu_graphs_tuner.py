@@ -152,6 +152,8 @@ def test_autotune_keeps_results_within_bar(torch, tmp_path, M, K, precision, fla
     ("precoder_mtiles", 2048, 128, 3, (1, 2, 4), bd.GRAM_FP32, 0),
     ("pcg_a_source", 0, 64, 0, (1, 2), bd.GRAM_BF16X6, 0),
     ("pcg_a_source", 0, 40, 0, (1, 2), bd.GRAM_FP32, 0),
+    ("pcg_a_source", 0, 128, 0, (2, 3), bd.GRAM_FP32, 0),
+    ("pcg_a_source", 0, 200, 0, (2, 3), bd.GRAM_BF16X6, 0),
 ])
 def test_every_tuned_choice_matches_the_oracle(torch, knob, M, K, variant, values, precision, flags):
     # Each value of each knob, pinned with jacpcg_tune_set, gives the precoder
@@ -174,8 +176,12 @@ def test_every_tuned_choice_matches_the_oracle(torch, knob, M, K, variant, value
                 err = np.linalg.norm(outs[-1][b].T - ref) / np.linalg.norm(ref)
                 print(f"{knob}={v} M={Mi} K={K}: err vs oracle {err:.2e}")
                 assert err <= 1e-5, (knob, v, err)
-    for o in outs[1:]:  # the choices change the launch, not the result beyond FP32 summation order
-        assert np.linalg.norm(o - outs[0]) <= 1e-6 * np.linalg.norm(outs[0])
+    # The choices change the launch and the FP32 summation order; above K = 64
+    # the solver's products are FP32 (2) or FP32-class split-BF16 (3), so
+    # there the results agree to the FP32 bar rather than to summation order.
+    bar = 1e-5 if knob == "pcg_a_source" and K > 64 else 1e-6
+    for o in outs[1:]:
+        assert np.linalg.norm(o - outs[0]) <= bar * np.linalg.norm(outs[0])
 
 
 def test_headline_full_size_in_the_benchmark_configuration(torch):
