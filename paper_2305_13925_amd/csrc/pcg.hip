@@ -229,12 +229,67 @@ __device__ __forceinline__ void apply_a_spl(floatx16& qr, floatx16& qi, const fl
   }
 }
 
+// Sparse form of the split-BF16 product: only the 32-column blocks of A that
+// can hold nonzeros in this wave's rows (bit c of `mask`) are taken, two
+// 16-row steps each, with both steps' entries loaded before the products.
+template <int KT>
+__device__ __forceinline__ void apply_a_spl_vr(floatx16& qr, floatx16& qi, const float2* __restrict__ arow,
+                                               bool rowvalid, int K, int ia, bool zero_diag, unsigned mask,
+                                               const u32x4* PB, int half, int jl) {
+  constexpr int K8 = KT * 4;
+  qr = zero16();
+  qi = zero16();
+  for (int c = 0; c < KT; ++c) {
+    if (!((mask >> c) & 1u)) continue;  // wave-uniform
+    float2 av[2][8];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int k = 32 * c + 16 * h + 8 * half + e;
+        av[h][e] = (rowvalid && k < K && !(zero_diag && k == ia)) ? arow[k] : make_float2(0.f, 0.f);
+      }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int st = 2 * c + h;
+      u32x4 Pr[3], Pi[3];
+#pragma unroll
+      for (int t = 0; t < 3; ++t) {
+        Pr[t] = PB[((0 * 3 + t) * K8 + 2 * st + half) * 32 + jl];
+        Pi[t] = PB[((1 * 3 + t) * K8 + 2 * st + half) * 32 + jl];
+      }
+      {
+        float re[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) re[e] = av[h][e].x;
+        u32x4 Ar[3];
+        split8<3>(re, Ar);
+        split_mma<3>(Ar, Pr, qr);
+        split_mma<3>(Ar, Pi, qi);
+      }
+      {
+        float im[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) im[e] = av[h][e].y;
+        u32x4 Ai[3];
+        split8<3>(im, Ai);
+        split_mma<3>(Ai, Pr, qi);
+#pragma unroll
+        for (int t = 0; t < 3; ++t)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) Ai[t][q] = neg_bf16x2(Ai[t][q]);
+        split_mma<3>(Ai, Pi, qr);
+      }
+    }
+  }
+}
+
 // Two waves per SIMD (the register budget of 256 per lane) let one workgroup's
 // reductions overlap another's products.
 template <int KT, bool AREG, bool VRS, bool SPL = false>
 __global__ __launch_bounds__(KT * 64) __attribute__((amdgpu_waves_per_eu(2))) void pcg_f32_kernel(PcgLaunch p) {
   static_assert(!(VRS && AREG), "the sparse variant streams A");
-  static_assert(!SPL || (!AREG && !VRS), "the split-BF16 product is for dense streamed A");
+  static_assert(!SPL || !AREG, "the split-BF16 product is for streamed A");
   constexpr int KP = KT * 32;
   constexpr int KH = KT * 16;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -424,7 +479,9 @@ __global__ __launch_bounds__(KT * 64) __attribute__((amdgpu_waves_per_eu(2))) vo
     ++t;
     __syncthreads();  // P visible to all waves
     floatx16 qr, qi;
-    if constexpr (VRS)
+    if constexpr (VRS && SPL)
+      apply_a_spl_vr<KT>(qr, qi, arow_full, ia < K, K, ia, false, vr_mask, PB, half, jl);
+    else if constexpr (VRS)
       apply_a_vr<KT>(qr, qi, arow_full, ia < K, K, ia, false, vr_mask, Psh, half, jl);
     else if constexpr (SPL)
       apply_a_spl<KT>(qr, qi, arow_full, ia < K, K, ia, false, PB, half, jl);
@@ -559,7 +616,9 @@ __global__ __launch_bounds__(KT * 64) __attribute__((amdgpu_waves_per_eu(2))) vo
     }
     __syncthreads();
     floatx16 yr, yi;
-    if constexpr (VRS)
+    if constexpr (VRS && SPL)
+      apply_a_spl_vr<KT>(yr, yi, arow_full, ia < K, K, ia, true, vr_mask, PB, half, jl);
+    else if constexpr (VRS)
       apply_a_vr<KT>(yr, yi, arow_full, ia < K, K, ia, true, vr_mask, Psh, half, jl);
     else if constexpr (SPL)
       apply_a_spl<KT>(yr, yi, arow_full, ia < K, K, ia, true, PB, half, jl);
@@ -601,6 +660,12 @@ template <int KT, bool AREG>
 hipError_t launch_kt(const PcgLaunch& p, int grid, hipStream_t s) {
   if constexpr (!AREG) {
     if (p.tile_span) {
+      if constexpr (KT >= 3) {
+        if (p.a_source != 2) {  // split-BF16 products (the default above K = 64)
+          hipLaunchKernelGGL((pcg_f32_kernel<KT, false, true, true>), dim3(grid), dim3(KT * 64), 0, s, p);
+          return hipGetLastError();
+        }
+      }
       hipLaunchKernelGGL((pcg_f32_kernel<KT, false, true>), dim3(grid), dim3(KT * 64), 0, s, p);
       return hipGetLastError();
     }
