@@ -537,22 +537,26 @@ def precision_rows(bd, torch, sess, stream, keep, reps=5):
 
 def stress_rows(bd, torch, sess, stream, keep, reps=3):
     """Stress workload: 64 x (M=8192 in 32 subarrays of 256, K=256), r=0.95,
-    regions of 1-3 subarrays, near-ZF xi = 1e-3, users in region order. FP32
-    Gram, complex64 Jacobi-PCG to relative residual 1e-6 (at most 4K = 1024
-    iterations), FP64-residual refinement to 1e-10 per column; dense path and
-    visibility-region sparse path, literal and gain-normalised channels (the
-    normalised gain is the literal one times 10^3.7 for every user). Per-column
-    iteration counts of the first solve; two instances per row come back for
-    the CPU leg's check against the FP64 direct inverse."""
+    regions of 1-3 subarrays, near-ZF xi = 1e-3, users in region order.
+    Complex64 Jacobi-PCG to relative residual 1e-6 (at most 4K = 1024
+    iterations) on the FP64 Gram that the refinement forms anyway, rounded
+    once to FP32, then FP64-residual refinement to 1e-10 per column; dense
+    path and visibility-region sparse path, literal and gain-normalised
+    channels (the normalised gain is the literal one times 10^3.7 for every
+    user). The same with a separate FP32 Gram for the solves under
+    *_fp32_gram. Per-column iteration counts of the first solve (FP32 Gram);
+    two instances per row come back for the CPU leg's check against the FP64
+    direct inverse."""
     from channelgen import sorted_channel_batch, workload
     ws = workload("stress")
     Hs_np, spans_np = sorted_channel_batch(ws)
     spans = torch.from_numpy(spans_np).to("cuda")
     out = {"config": f"{ws.batch} x (M={ws.M} = {ws.S} x {ws.M // ws.S}, K={ws.K}), r={ws.r}, regions of "
-                     f"{ws.vr[0]}-{ws.vr[1]}, xi={ws.xi:g}, users in region order, FP32 Gram, PCG to 1e-6 "
-                     f"(<= 1024 iterations), FP64 refinement to {REFINE_TOL:g} per column"}
+                     f"{ws.vr[0]}-{ws.vr[1]}, xi={ws.xi:g}, users in region order, PCG to 1e-6 (<= 1024 "
+                     f"iterations) on the FP64 Gram rounded to FP32 (a separate FP32 Gram under *_fp32_gram), "
+                     f"FP64 refinement to {REFINE_TOL:g} per column"}
     picks = (0, ws.batch - 1)
-    prec = bd.GRAM_FP32 | bd.REFINE_FP64
+    prec = bd.GRAM_FP64_ROUNDED | bd.REFINE_FP64
     autotune(sess, ws.batch, ws.M, ws.K, bd.GRAM_FP32, 0, stream)
     for gain in ("literal", "normalised"):
         H = torch.from_numpy(Hs_np).to("cuda")
@@ -583,6 +587,24 @@ def stress_rows(bd, torch, sess, stream, keep, reps=3):
                          "max_pcg_iters": st["max_iters"], "refine_steps": st["refine_steps"],
                          "max_refine_residual": st["max_refine_residual"],
                          "phases_us": _phases_us(sess, run, 2)}
+        # The same with a separate FP32 Gram for the solves.
+        p32 = bd.GRAM_FP32 | bd.REFINE_FP64
+        for path in ("dense", "vr"):
+            if path == "dense":
+                run = lambda: bd.rzf_precoder(sess, H, ws.xi, tol=1e-6, max_iter=1024, precision=p32,
+                                              refine_tol=REFINE_TOL, W=W, stream=stream)
+                _, st, rc = bd.rzf_precoder(sess, H, ws.xi, tol=1e-6, max_iter=1024, precision=p32,
+                                            refine_tol=REFINE_TOL, W=W, stats=True, stream=stream)
+            else:
+                run = lambda: bd.rzf_precoder_vr(sess, H, ws.xi, user_span=spans, tol=1e-6, max_iter=1024,
+                                                 precision=p32, refine_tol=REFINE_TOL, W=W, stream=stream)
+                _, st, rc = bd.rzf_precoder_vr(sess, H, ws.xi, user_span=spans, tol=1e-6, max_iter=1024,
+                                               precision=p32, refine_tol=REFINE_TOL, W=W, stats=True,
+                                               stream=stream)
+            ms = _timed_ms(torch, stream, run, reps)
+            rec[path + "_fp32_gram"] = {"ms": round(ms, 3), "status": rc, "max_pcg_iters": st["max_iters"],
+                                        "refine_steps": st["refine_steps"],
+                                        "max_refine_residual": st["max_refine_residual"]}
         rec["vr_speedup"] = round(rec["dense"]["ms"] / rec["vr"]["ms"], 2)
         out[gain] = rec
         del H, W, X64

@@ -415,13 +415,15 @@ def test_refined_reaches_fp64(torch, sess, prec, name, gain, n, tol, T):
         assert ew <= 1e-6          # W is complex64: only its rounding remains
 
 
-def test_refined_stress_sampled(torch, sess):
-    # Near-ZF regularisation, strong correlation: ill-conditioned systems.
+@pytest.mark.parametrize("gram", [bd.GRAM_FP32, bd.GRAM_FP64_ROUNDED])
+def test_refined_stress_sampled(torch, sess, gram):
+    # Near-ZF regularisation, strong correlation: ill-conditioned systems. The
+    # solves on the FP32 Gram or on the FP64 Gram rounded to FP32.
     w = workload("stress")
     H = channel_batch(w, n=2)
     X64 = torch.empty((2, w.K, w.K), dtype=torch.complex128, device="cuda")
     W, st, rc = bd.rzf_precoder(sess, dev(torch, H), w.xi, tol=1e-6, max_iter=1024,
-                                precision=bd.GRAM_FP32 | bd.REFINE_FP64, refine_tol=REFINE_TOL, X64_out=X64,
+                                precision=gram | bd.REFINE_FP64, refine_tol=REFINE_TOL, X64_out=X64,
                                 stats=True)
     assert rc == bd.OK, st
     Xn = X64.cpu().numpy()

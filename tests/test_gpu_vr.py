@@ -109,15 +109,17 @@ def test_vr_stress_full_size_refined_sampled(torch, sess):
         assert e <= 1e-6
 
 
-def test_vr_refined_x_matches_the_fp64_inverse(torch, sess):
+@pytest.mark.parametrize("gram", [bd.GRAM_FP32, bd.GRAM_FP64_ROUNDED])
+def test_vr_refined_x_matches_the_fp64_inverse(torch, sess, gram):
     # The refined sparse path forms its FP64 Gram over each block's antenna
     # overlap only. Its X (rounded once from X64 to complex64) against the
     # FP64 direct inverse and against the refined dense path: a block missing
     # a nonzero channel entry would leave X off by far more than the rounding.
+    # The solves take the FP32 Gram or the FP64 Gram rounded to FP32.
     w = small_stress(128)
     H, spans = sorted_channel_batch(w, n=2)
     Hd = torch.from_numpy(H).cuda()
-    prec = bd.GRAM_FP32 | bd.REFINE_FP64
+    prec = gram | bd.REFINE_FP64
     X_vr = torch.empty((2, w.K, w.K), dtype=torch.complex64, device="cuda")
     X_dn = torch.empty_like(X_vr)
     _, st, rc = bd.rzf_precoder_vr(sess, Hd, 1e-2, user_span=torch.from_numpy(spans).cuda(), tol=1e-6,
