@@ -3,6 +3,7 @@
 #include "session.hpp"
 
 #include <algorithm>
+#include <functional>
 #include <cmath>
 #include <cstring>
 #include <limits>
@@ -712,22 +713,30 @@ int jacpcg_session::autotune(hipStream_t st, int batch, int M, int K, int precis
   float* fpart = at<float>(oF);
   S_HIP(launch_fill_synthetic(H, (size_t)batch * M * K, 12345u, st));
   hipEvent_t e0 = get_event(), e1 = get_event();
-  auto time_it = [&](auto&& launch) -> float {
-    if (launch() != hipSuccess) {  // warm-up (code object load, caches); a choice the kernel rejects
-      (void)hipGetLastError();
-      return 1e30f;
+  // Times a set of launch choices: each launched once first (code object
+  // load, caches; a choice the kernel rejects counts as infinitely slow), then
+  // five rounds that launch every choice once in turn, keeping each choice's
+  // fastest launch. Round-robin puts any drift of the GPU's speed over the
+  // tuning time (the first tens of milliseconds after allocation run slower)
+  // on all choices alike; the fastest launch is the one other work on the GPU
+  // disturbed least.
+  auto time_all = [&](const std::vector<std::function<hipError_t()>>& fns) {
+    std::vector<float> best(fns.size(), 1e30f);
+    std::vector<bool> ok(fns.size(), false);
+    for (size_t i = 0; i < fns.size(); ++i) {
+      ok[i] = fns[i]() == hipSuccess;
+      if (!ok[i]) (void)hipGetLastError();
     }
-    // Fastest of five single launches: choices a few percent apart are told
-    // apart by their best case, which other work on the GPU disturbs least.
-    float best = 1e30f;
-    for (int r = 0; r < 5; ++r) {
-      (void)hipEventRecord(e0, st);
-      (void)launch();
-      (void)hipEventRecord(e1, st);
-      (void)hipEventSynchronize(e1);
-      float ms = 1e30f;
-      if (hipEventElapsedTime(&ms, e0, e1) == hipSuccess && ms < best) best = ms;
-    }
+    for (int r = 0; r < 5; ++r)
+      for (size_t i = 0; i < fns.size(); ++i) {
+        if (!ok[i]) continue;
+        (void)hipEventRecord(e0, st);
+        (void)fns[i]();
+        (void)hipEventRecord(e1, st);
+        (void)hipEventSynchronize(e1);
+        float ms = 1e30f;
+        if (hipEventElapsedTime(&ms, e0, e1) == hipSuccess && ms < best[i]) best[i] = ms;
+      }
     return best;
   };
   GramLaunch g{};
@@ -746,15 +755,17 @@ int jacpcg_session::autotune(hipStream_t st, int batch, int M, int K, int precis
   // Each knob in turn: time every valid value on the synthetic batch and keep
   // the fastest (the earlier knobs already at their chosen values).
   auto pick = [&](int knob, int Mk, int Kk, int variant, std::initializer_list<int> values, auto&& launch_with) {
+    const std::vector<int> vals(values);
+    std::vector<std::function<hipError_t()>> fns;
+    for (int v : vals) fns.push_back([&launch_with, v] { return launch_with(v); });
+    const std::vector<float> t = time_all(fns);
     int best = 0;
     float best_t = 1e30f;
-    for (int v : values) {
-      const float t = time_it([&] { return launch_with(v); });
-      if (t < best_t) {
-        best_t = t;
-        best = v;
+    for (size_t i = 0; i < vals.size(); ++i)
+      if (t[i] < best_t) {
+        best_t = t[i];
+        best = vals[i];
       }
-    }
     tuner.set(knob, Mk, Kk, variant, best);
     return best;
   };
@@ -811,22 +822,31 @@ int jacpcg_session::autotune(hipStream_t st, int batch, int M, int K, int precis
   // interact, so they are searched together.
   const bool tune_nj = K <= 128 && K > 32, tune_mt = E.split == 3;
   if (tune_nj || tune_mt) {
-    int best_nj = 0, best_mt = 0;
-    float best_t = 1e30f;
+    std::vector<std::pair<int, int>> cand;  // (column tiles, antenna blocks)
     for (int nj : {1, 2}) {
       if (!tune_nj && nj > 1) break;
       for (int mt : {1, 2, 4}) {
         if (!tune_mt && mt > 1) break;
-        E.nj = tune_nj ? nj : 0;
-        E.mtiles = tune_mt ? mt : 0;
-        const float t = time_it([&] { return launch_precoder(E, st); });
-        if (t < best_t) {
-          best_t = t;
-          best_nj = E.nj;
-          best_mt = E.mtiles;
-        }
+        cand.emplace_back(tune_nj ? nj : 0, tune_mt ? mt : 0);
       }
     }
+    std::vector<std::function<hipError_t()>> fns;
+    for (const auto& c : cand)
+      fns.push_back([&E, &st, c] {
+        PrecoderLaunch e = E;
+        e.nj = c.first;
+        e.mtiles = c.second;
+        return launch_precoder(e, st);
+      });
+    const std::vector<float> t = time_all(fns);
+    int best_nj = 0, best_mt = 0;
+    float best_t = 1e30f;
+    for (size_t i = 0; i < cand.size(); ++i)
+      if (t[i] < best_t) {
+        best_t = t[i];
+        best_nj = cand[i].first;
+        best_mt = cand[i].second;
+      }
     if (tune_nj) tuner.set(kPrecoderNj, M, K, E.split, best_nj);
     if (tune_mt) tuner.set(kPrecoderMtiles, M, K, E.split, best_mt);
   }
