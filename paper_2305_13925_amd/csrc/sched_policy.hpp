@@ -33,9 +33,13 @@ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Device workspace of one batch of G instances with K users, in launch order:
 // instance pointer arrays, A, diag(H^H H), X, per-workgroup partials and
-// statuses, per-column iterations and residuals.
+// statuses, per-column iterations and residuals, and above K = 128 the
+// partial 64 x 64 blocks of an FP32 Gram summed over kGramChunks antenna
+// chunks.
+constexpr int kGramChunks = 4;
+inline int gram_chunks_for(int K) { return K > 128 ? kGramChunks : 1; }
 struct BatchLayout {
-  size_t hp, wp, a, gd, x, fp, wg, st, it, rr, total;
+  size_t hp, wp, a, gd, x, fp, wg, st, it, rr, part, total;
   BatchLayout(int G, int K) {
     const int ncb = (K + 31) / 32;
     size_t o = 0;
@@ -54,6 +58,8 @@ struct BatchLayout {
     st = take((size_t)G * 4);
     it = take((size_t)G * K * 4);
     rr = take((size_t)G * K * 4);
+    const int nb = (K + 63) / 64, chunks = gram_chunks_for(K);
+    part = chunks > 1 ? take((size_t)G * (nb * (nb + 1) / 2) * chunks * 64 * 64 * 8) : 0;
     total = o;
   }
 };
