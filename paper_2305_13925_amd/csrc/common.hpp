@@ -172,8 +172,8 @@ size_t pcg_state_floats_per_wg(int K);
 hipError_t launch_status_reduce(const int32_t* wg_status, int ncb, int batch, int32_t* status, hipStream_t s);
 hipError_t launch_precoder(const PrecoderLaunch& e, hipStream_t s);
 hipError_t launch_gram64(const Gram64Launch& g, hipStream_t s);
-int gram64_antenna_chunks(int K, bool spans);  // antenna chunks of the FP64 Gram (1: unsplit)
-int gram_antenna_chunks(int K, int precision, bool spans);  // the same for the FP32 Gram
+int gram64_antenna_chunks(int K, int batch, bool spans);  // antenna chunks of the FP64 Gram (1: unsplit)
+int gram_antenna_chunks(int K, int batch, int precision, bool spans);  // the same for the FP32 Gram
 hipError_t launch_narrow_gram(const double2* A64, int K, int batch, double xi, float2* A, int64_t lda,
                               int64_t stride_a, float* gdiag, hipStream_t s);
 hipError_t launch_refine_step(const RefineStepLaunch& r, hipStream_t s);

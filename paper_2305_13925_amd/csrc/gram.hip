@@ -887,12 +887,16 @@ hipError_t launch_gram(const GramLaunch& g, hipStream_t s) {
   return hipGetLastError();
 }
 
-int gram_antenna_chunks(int K, int precision, bool spans) {
-  // The FP32 block kernel above K = 128 without spans: 64 instances of
+int gram_antenna_chunks(int K, int batch, int precision, bool spans) {
+  // The FP32 block kernel without spans. Above K = 128: 64 instances of
   // K = 256 give 640 workgroups for 768 slots (2.5 per compute unit), so the
   // compute units holding three set the time; four antenna chunks per block
-  // give ten equal workgroups per compute unit.
-  return (precision == 0 && K > 128 && !spans) ? 4 : 1;
+  // give ten equal workgroups per compute unit. Above K = 64 with fewer than
+  // 512 blocks in the batch, the chunks fill idle compute units; with every
+  // block resident at once (256 instances of K = 128) they only add the sums.
+  const int nb = (K + 63) / 64;
+  const long items = (long)batch * (nb * (nb + 1) / 2);
+  return (precision == 0 && !spans && (K > 128 || (K > 64 && items < 512))) ? 4 : 1;
 }
 
 }  // namespace jacpcg

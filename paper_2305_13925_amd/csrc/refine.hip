@@ -608,11 +608,15 @@ hipError_t launch_gram64(const Gram64Launch& g, hipStream_t s) {
   return hipGetLastError();
 }
 
-int gram64_antenna_chunks(int K, bool spans) {
+int gram64_antenna_chunks(int K, int batch, bool spans) {
   // Above K = 128 a batch has few 64 x 64 blocks of unequal work (diagonal
   // blocks form 10 of their 16 tiles) for the compute units; four antenna
-  // chunks per block even out the load. Not with spans (sparse blocks).
-  return (K > 2 * kG64Rows && !spans) ? 4 : 1;
+  // chunks per block even out the load. Above K = 64 the same when the batch
+  // has fewer than 512 blocks (idle compute units). Not with spans (sparse
+  // blocks).
+  const int nb = (K + kG64Rows - 1) / kG64Rows;
+  const long items = (long)batch * (nb * (nb + 1) / 2);
+  return (!spans && (K > 2 * kG64Rows || (K > kG64Rows && items < 512))) ? 4 : 1;
 }
 
 hipError_t launch_narrow_gram(const double2* A64, int K, int batch, double xi, float2* A, int64_t lda,

@@ -401,10 +401,10 @@ int Scheduler::launch(Slot& sl, const std::vector<uint64_t>& members, const std:
   g.precision = r0.precision;
   g.m_split = s_->tuner.gram_waves(M, K, r0.precision);
   g.no_vec = vec_ok ? 0 : 1;
-  // Antenna chunks of the FP32 Gram above K = 128 (the launch uses them for
-  // the FP32 block kernel only): four times the workgroups, which fills the
-  // GPU for a few subcarriers (the layout holds their partial blocks).
-  g.msplit = gram_chunks_for(K);
+  // Antenna chunks of the FP32 Gram (the launch uses them for the FP32 block
+  // kernel only): four times the workgroups, which fills the GPU for a few
+  // subcarriers (the layout holds their partial blocks).
+  g.msplit = gram_chunks_for(K, G);
   g.partial = g.msplit > 1 ? (float2*)(ws + lay.part) : nullptr;
   if (e == hipSuccess) e = launch_gram(g, st);
 

@@ -36,8 +36,16 @@ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 // statuses, per-column iterations and residuals, and above K = 128 the
 // partial 64 x 64 blocks of an FP32 Gram summed over kGramChunks antenna
 // chunks.
+// Four chunks above K = 128, and above K = 64 when the batch has fewer than
+// 512 blocks of A (two per compute unit): the chunks then fill idle compute
+// units. (With every block resident at once, as 256 instances of K = 128 are,
+// chunks only add the partial sums.)
 constexpr int kGramChunks = 4;
-inline int gram_chunks_for(int K) { return K > 128 ? kGramChunks : 1; }
+inline int gram_chunks_for(int K, int batch) {
+  const int nb = (K + 63) / 64;
+  const long items = (long)batch * (nb * (nb + 1) / 2);
+  return (K > 128 || (K > 64 && items < 512)) ? kGramChunks : 1;
+}
 struct BatchLayout {
   size_t hp, wp, a, gd, x, fp, wg, st, it, rr, part, total;
   BatchLayout(int G, int K) {
@@ -58,7 +66,7 @@ struct BatchLayout {
     st = take((size_t)G * 4);
     it = take((size_t)G * K * 4);
     rr = take((size_t)G * K * 4);
-    const int nb = (K + 63) / 64, chunks = gram_chunks_for(K);
+    const int nb = (K + 63) / 64, chunks = gram_chunks_for(K, G);
     part = chunks > 1 ? take((size_t)G * (nb * (nb + 1) / 2) * chunks * 64 * 64 * 8) : 0;
     total = o;
   }

@@ -212,9 +212,9 @@ int jacpcg_session::run_rzf(hipStream_t st, int batch, int M, int K, const float
   const size_t oTS = use_spans ? ws.take<int2>((size_t)batch * nt) : 0;
   // FP64 and FP32 Grams in antenna chunks: their partial 64 x 64 blocks, one
   // buffer for both (launched one after the other on the same stream)
-  const int g64_chunks = refine ? gram64_antenna_chunks(K, use_spans) : 1;
+  const int g64_chunks = refine ? gram64_antenna_chunks(K, batch, use_spans) : 1;
   const bool fp32_class_gram = !(refine && gram_prec == JACPCG_GRAM_FP64_ROUNDED);
-  const int g32_chunks = fp32_class_gram ? gram_antenna_chunks(K, gram_prec, use_spans) : 1;
+  const int g32_chunks = fp32_class_gram ? gram_antenna_chunks(K, batch, gram_prec, use_spans) : 1;
   const int g_nb = (K + 63) / 64;
   const size_t part_blocks = (size_t)batch * (g_nb * (g_nb + 1) / 2) * 64 * 64;
   const size_t part_d2 = std::max(g64_chunks > 1 ? part_blocks * g64_chunks : 0,
@@ -581,6 +581,12 @@ int jacpcg_session::run_rzf_plain(hipStream_t st, int batch, int M, int K, const
   const size_t oSV = ws.take<float>(pcg_state_floats_per_wg(K) * ncb);
   const size_t oSC = ws.take<float>((size_t)8 * 32 * ncb);
   const size_t oSD = ws.take<int32_t>(ncb);
+  // The Gram in as many antenna chunks as the batched call takes for this
+  // batch, so that both paths give the same A (partial blocks of one instance).
+  const int g32_chunks = gram_antenna_chunks(K, batch, 0, false);
+  const int g_nb = (K + 63) / 64;
+  const size_t oPart =
+      g32_chunks > 1 ? ws.take<float2>((size_t)(g_nb * (g_nb + 1) / 2) * g32_chunks * 64 * 64) : 0;
   if (int rc = reserve(ws)) return rc;
   float2* A = at<float2>(oA);
   float* gdiag = at<float>(oG);
@@ -611,6 +617,8 @@ int jacpcg_session::run_rzf_plain(hipStream_t st, int batch, int M, int K, const
     g.gdiag = gdiag;
     g.precision = 0;
     g.m_split = tuner.gram_waves(M, K, 0);
+    g.msplit = g32_chunks;
+    g.partial = g32_chunks > 1 ? at<float2>(oPart) : nullptr;
     hipError_t e = timed(st, JACPCG_PHASE_GRAM, [&] { return launch_gram(g, st); });
     if (e != hipSuccess) return hip_error(this, e, "gram launch");
 
