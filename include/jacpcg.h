@@ -247,7 +247,8 @@ typedef struct {
  *   at most 16 corrections. The power factor comes from ||H X64||_F^2 in FP64
  *   and W from X64 rounded to FP32. An instance with a column still above
  *   refine_tol after 16 corrections reports NOT_CONVERGED.
- * Above K = 128 (without visibility-region spans) the FP32 Gram and the FP64
+ * Above K = 128, and above K = 64 when the batch has fewer than 512 64 x 64
+ *   blocks of A (without visibility-region spans), the FP32 Gram and the FP64
  *   Gram of this call sum the antennas in four chunks, added in a fixed order
  *   (session workspace: 4 partial 64 x 64 blocks per block of A); the FP32 A
  *   can then differ from jacpcg_gram's in the last bits.
