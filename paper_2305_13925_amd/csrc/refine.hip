@@ -38,16 +38,21 @@ __device__ __forceinline__ void upper_tile16(int t, int nt, int& ti, int& tj) {
 // 16 x 16 tiles, so no reduction across waves); in a diagonal block the tiles
 // wholly below the diagonal are not formed. The channel rows of the block
 // pass through LDS 16 antennas at a time, widened to FP64 once as they are
-// stored: the row operand as (-Im, Re, Im) triples, the column operand as
-// (Re, Im) pairs, so every MFMA operand is a single LDS read:
-//   Re A_ij += (Re h_i, Im h_i) . (Re h_j, Im h_j)   over the slots comp = 0, 1
-//   Im A_ij += (-Im h_i, Re h_i) . (Re h_j, Im h_j)
+// stored. Each entry conj(h_i) h_j = (a - ib)(c + id) takes three real
+// products instead of four (Gauss's method):
+//   t1 = a c,  t2 = b d,  t3 = (a - b)(c + d);
+//   Re A_ij = t1 + t2,  Im A_ij = (t3 - t1) + t2 = a d - b c,
+// each summed over the antennas on its own accumulator, the four k slots of
+// one MFMA carrying four antennas. The row operand is stored as (a, b, a - b)
+// triples and the column operand as (c, d, c + d), so every MFMA operand is
+// a single LDS read. Im A_ij picks up rounding of the size of the terms'
+// magnitudes, the same order as the four-product sum's; the diagonal's
+// imaginary part is set to exactly zero.
 // Global loads are coalesced 16-byte loads one stage ahead (into registers)
 // of the products.
 constexpr int kG64Rows = 64;  // block edge
 constexpr int kG64Ant = 16;   // antennas per stage
-constexpr int kG64PitchA = 3 * kG64Ant + 1;  // doubles per row operand row (+1: bank spread)
-constexpr int kG64PitchB = 2 * kG64Ant + 1;  // doubles per column operand row
+constexpr int kG64Pitch = 3 * kG64Ant + 1;  // doubles per operand row (+1: bank spread)
 
 __global__ __launch_bounds__(256) void gram64_kernel(Gram64Launch g) {
   const int nb = (g.K + kG64Rows - 1) / kG64Rows;
@@ -64,14 +69,13 @@ __global__ __launch_bounds__(256) void gram64_kernel(Gram64Launch g) {
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int q = lane >> 4, li = lane & 15;
-  const int slot_m = q >> 1, comp = q & 1;
   const float2* Hb = g.H + (int64_t)b * g.stride_h;
   const bool vec = ((uintptr_t)g.H % 16 == 0) && (g.ldh % 2 == 0) && (g.stride_h % 2 == 0);
 
   // Row operand (block rows i) and column operand (block columns j); a
-  // diagonal block stages only the row operand and reads it for both.
-  __shared__ double HsA[kG64Rows][kG64PitchA];
-  __shared__ double HsB[kG64Rows][kG64PitchB];
+  // diagonal block loads its rows once and stores both operands from them.
+  __shared__ double HsA[kG64Rows][kG64Pitch];
+  __shared__ double HsB[kG64Rows][kG64Pitch];
 
   // Stage loads: each thread moves 2 x 16 bytes per operand (row = e / 8,
   // antennas 2 (e % 8) and 2 (e % 8) + 1 of the stage).
@@ -113,48 +117,45 @@ __global__ __launch_bounds__(256) void gram64_kernel(Gram64Launch g) {
       const int row = e >> 3, a2 = 2 * (e & 7);
       const float4 v = st[0][u];
       double* d = &HsA[row][3 * a2];
-      d[0] = -(double)v.y;
-      d[1] = (double)v.x;
-      d[2] = (double)v.y;
-      d[3] = -(double)v.w;
-      d[4] = (double)v.z;
-      d[5] = (double)v.w;
-      if (!same) {
-        const float4 c = st[1][u];
-        double* f = &HsB[row][2 * a2];
-        f[0] = (double)c.x;
-        f[1] = (double)c.y;
-        f[2] = (double)c.z;
-        f[3] = (double)c.w;
-      }
+      d[0] = (double)v.x;
+      d[1] = (double)v.y;
+      d[2] = (double)v.x - (double)v.y;
+      d[3] = (double)v.z;
+      d[4] = (double)v.w;
+      d[5] = (double)v.z - (double)v.w;
+      const float4 c = same ? v : st[1][u];
+      double* f = &HsB[row][3 * a2];
+      f[0] = (double)c.x;
+      f[1] = (double)c.y;
+      f[2] = (double)c.x + (double)c.y;
+      f[3] = (double)c.z;
+      f[4] = (double)c.w;
+      f[5] = (double)c.z + (double)c.w;
     }
   };
 
-  doublex4 accR[4], accI[4];
+  doublex4 t1[4], t2[4], t3[4];
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
-    accR[c] = zero4d();
-    accI[c] = zero4d();
+    t1[c] = zero4d();
+    t2[c] = zero4d();
+    t3[c] = zero4d();
   }
   // The products of one stage for NT tiles (row tile R[t] of the row operand,
-  // column tile C[t] of the column operand, or of the row operand on the
-  // diagonal: OPJ 1 or 0). Called with compile-time tile lists, so every LDS
-  // offset is static and every product is unconditional.
-  auto products = [&](auto nt_tag, auto opj_tag, const int (&R)[4], const int (&C)[4]) {
+  // column tile C[t] of the column operand). Called with compile-time tile
+  // lists, so every LDS offset is static and every product is unconditional.
+  auto products = [&](auto nt_tag, const int (&R)[4], const int (&C)[4]) {
     constexpr int NT = decltype(nt_tag)::value;
-    constexpr int OPJ = decltype(opj_tag)::value;
-#pragma unroll 2  // full unrolling hoists every operand: one wave per SIMD
-    for (int p = 0; p < kG64Ant / 2; ++p) {
-      // k slot q: antenna 2p + slot_m, component comp.
-      const int ant = 2 * p + slot_m;
+#pragma unroll  // the operands of the four steps are loaded ahead
+    for (int p = 0; p < kG64Ant / 4; ++p) {
+      const int ant = 4 * p + q;  // k slot q
 #pragma unroll
       for (int c = 0; c < NT; ++c) {
         const double* ra = &HsA[16 * R[c] + li][3 * ant];
-        const double a_plain = ra[1 + comp];  // (Re, Im)[comp]
-        const double a_rot = ra[comp];        // (-Im, Re)[comp]
-        const double bv = OPJ ? HsB[16 * C[c] + li][2 * ant + comp] : HsA[16 * C[c] + li][3 * ant + 1 + comp];
-        accR[c] = mfma64(a_plain, bv, accR[c]);
-        accI[c] = mfma64(a_rot, bv, accI[c]);
+        const double* cb = &HsB[16 * C[c] + li][3 * ant];
+        t1[c] = mfma64(ra[0], cb[0], t1[c]);
+        t2[c] = mfma64(ra[1], cb[1], t2[c]);
+        t3[c] = mfma64(ra[2], cb[2], t3[c]);
       }
     }
   };
@@ -168,13 +169,13 @@ __global__ __launch_bounds__(256) void gram64_kernel(Gram64Launch g) {
   const int ntile = same ? (w < 2 ? 3 : 2) : 4;
   auto stage = [&]() {
     if (!same) {
-      products(std::integral_constant<int, 4>{}, std::integral_constant<int, 1>{}, offR, offC);
+      products(std::integral_constant<int, 4>{}, offR, offC);
     } else {
       switch (w) {  // wave-uniform
-        case 0: products(std::integral_constant<int, 3>{}, std::integral_constant<int, 0>{}, kDiagR[0], kDiagC[0]); break;
-        case 1: products(std::integral_constant<int, 3>{}, std::integral_constant<int, 0>{}, kDiagR[1], kDiagC[1]); break;
-        case 2: products(std::integral_constant<int, 2>{}, std::integral_constant<int, 0>{}, kDiagR[2], kDiagC[2]); break;
-        default: products(std::integral_constant<int, 2>{}, std::integral_constant<int, 0>{}, kDiagR[3], kDiagC[3]); break;
+        case 0: products(std::integral_constant<int, 3>{}, kDiagR[0], kDiagC[0]); break;
+        case 1: products(std::integral_constant<int, 3>{}, kDiagR[1], kDiagC[1]); break;
+        case 2: products(std::integral_constant<int, 2>{}, kDiagR[2], kDiagC[2]); break;
+        default: products(std::integral_constant<int, 2>{}, kDiagR[3], kDiagC[3]); break;
       }
     }
   };
@@ -238,7 +239,8 @@ __global__ __launch_bounds__(256) void gram64_kernel(Gram64Launch g) {
       const int tc = same ? kDiagC[wq][c] : c;
 #pragma unroll
       for (int r = 0; r < 4; ++r)
-        Pb[(16 * tr + q + 4 * r) * kG64Rows + 16 * tc + li] = make_double2(accR[c][r], accI[c][r]);
+        Pb[(16 * tr + q + 4 * r) * kG64Rows + 16 * tc + li] =
+            make_double2(t1[c][r] + t2[c][r], (t3[c][r] - t1[c][r]) + t2[c][r]);
     }
     return;
   }
@@ -253,7 +255,7 @@ __global__ __launch_bounds__(256) void gram64_kernel(Gram64Launch g) {
       const int gi = bi * kG64Rows + 16 * tr + q + 4 * r;
       const int gj = bj * kG64Rows + 16 * tc + li;
       if (gi >= g.K || gj >= g.K || gi > gj) continue;
-      const double re = accR[c][r], im = accI[c][r];
+      const double re = t1[c][r] + t2[c][r], im = (t3[c][r] - t1[c][r]) + t2[c][r];
       if (gi == gj) {
         Ab[(int64_t)gi * g.K + gj] = make_double2(re + g.xi, 0.0);
       } else {
@@ -612,11 +614,14 @@ int gram64_antenna_chunks(int K, int batch, bool spans) {
   // Above K = 128 a batch has few 64 x 64 blocks of unequal work (diagonal
   // blocks form 10 of their 16 tiles) for the compute units; four antenna
   // chunks per block even out the load. Above K = 64 the same when the batch
-  // has fewer than 512 blocks (idle compute units). Not with spans (sparse
+  // has fewer than 512 blocks (idle compute units), and two chunks with more:
+  // two workgroups fit a compute unit, so 768 blocks (256 instances of
+  // K = 128) would run in one and a half rounds. Not with spans (sparse
   // blocks).
+  if (spans || K <= kG64Rows) return 1;
   const int nb = (K + kG64Rows - 1) / kG64Rows;
   const long items = (long)batch * (nb * (nb + 1) / 2);
-  return (!spans && (K > 2 * kG64Rows || (K > kG64Rows && items < 512))) ? 4 : 1;
+  return (K > 2 * kG64Rows || items < 512) ? 4 : 2;
 }
 
 hipError_t launch_narrow_gram(const double2* A64, int K, int batch, double xi, float2* A, int64_t lda,
