@@ -251,7 +251,8 @@ typedef struct {
  *   blocks of A (without visibility-region spans), the FP32 Gram and the FP64
  *   Gram of this call sum the antennas in four chunks, added in a fixed order
  *   (session workspace: 4 partial 64 x 64 blocks per block of A); the FP32 A
- *   can then differ from jacpcg_gram's in the last bits.
+ *   can then differ from jacpcg_gram's in the last bits. Above K = 64 with
+ *   512 or more blocks the FP64 Gram sums two chunks.
  * X_out (nullable): column-major K x K c64 copy of X per instance (ld K,
  *   stride K*K). X64_out (nullable): the same in c128 (the refined X64; the
  *   FP32 solution widened otherwise). flags: as jacpcg_solve.
